@@ -1,0 +1,199 @@
+/*
+ * gridplan.h - C ABI of libgridplan, the MI355X (gfx950) hot path of
+ * implicit-gradient expansion planning (Degleris, El Gamal, Rajagopal,
+ * "Scalable and Interactive Electricity Grid Expansion Planning").
+ *
+ * Problem (Section 2.1, eq. (1) and eq. (2)):
+ *   minimise over eta in [eta_min, eta_max]
+ *       gamma' eta + (1/S) sum_s w_s h_s(x*_s(eta)),
+ *   x*_s(eta) = argmin_x c_s(x) s.t. A_s(eta) x <= b_s(eta)   (dispatch map)
+ * Gradient and update (Section 2.2):
+ *   Delta = gamma + (1/S) sum_s (d x*_s/d eta)' grad h_s(x*_s),
+ *   eta <- proj_[eta_min, eta_max](eta - alpha * Delta).
+ *
+ * Dispatch model of one scenario (hours t = 0..T-1, 1 h each):
+ *   p[g,t] in [0, avail[g,t] * eta_g]     generator output
+ *   f[l,t] in [-eta_l, eta_l]             line flow from -> to
+ *   th[n,t] free                          bus angle
+ *   ch[k,t], dis[k,t] in [0, eta_k]       battery charge / discharge
+ *   soc[k,t] in [0, hours * eta_k]        battery state of charge
+ *   u[n,t] >= 0                           unserved load
+ *   balance: sum_{g@n} p + sum_{k@n}(dis - ch) + u + sum_{l:to=n} f
+ *            - sum_{l:from=n} f = load[n,t]             (dual: price pi)
+ *   flow:    f - beta_l (th[from] - th[to]) = 0         (dual: mu)
+ *   soc:     soc[t] - soc[t-1] - eff ch[t] + dis[t] = 0, cyclic (dual: nu)
+ *   c_s(x) = sum cost_g p + lambda_u sum u + (r/2) ||x||^2
+ *   h_s(x) = c_s(x) + omega * sum emis_g p   (emissions-aware planning)
+ *
+ * Canonical per-scenario vector orders (used by the accessors):
+ *   x = [p (G*T) | f (L*T) | th (N*T) | ch (B*T) | dis (B*T) | soc (B*T) | u (N*T)]
+ *   y = [pi (N*T) | mu (L*T) | nu (B*T)], every block [device][hour].
+ * Capacity vector per network: eta = [generators | lines | batteries];
+ * across networks the vectors are concatenated in network order (K total).
+ *
+ * Conventions:
+ *   - All pointers in the descriptors and call arguments are HOST pointers
+ *     unless stated otherwise; the library copies what it keeps.  Callers
+ *     own every buffer they pass; nothing is retained after a call returns.
+ *   - Every call validates its arguments on the host before touching the
+ *     GPU; a negative return is an error and leaves the plan unchanged
+ *     (plan_last_error() then describes it).  GP_ENOTCONVERGED (> 0) means
+ *     results were written but some scenario missed the tolerance.
+ *   - All device work runs on the HIP stream given to plan_init.  Calls on
+ *     one plan are not thread-safe.
+ */
+#ifndef GRIDPLAN_H
+#define GRIDPLAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GP_OK 0
+#define GP_ENOTCONVERGED 1
+#define GP_EINVAL (-1)
+#define GP_ENOMEM (-2)
+#define GP_EHIP (-3)
+#define GP_ESTATE (-4)
+
+typedef struct gp_plan gp_plan;
+
+/* One transmission network and its plannable devices (Section 2.1: eta
+ * holds generator, line and storage capacities). */
+typedef struct {
+  int32_t n_nodes, n_lines, n_gens, n_batt;
+  const int32_t* line_from;  /* [n_lines] node index in [0, n_nodes) */
+  const int32_t* line_to;    /* [n_lines] node index, != line_from */
+  const double* line_beta;   /* [n_lines] susceptance, > 0 */
+  const int32_t* gen_node;   /* [n_gens] */
+  const double* gen_cost;    /* [n_gens] marginal cost, $/MWh, >= 0 */
+  const double* gen_emis;    /* [n_gens] emission rate, t/MWh, >= 0 */
+  const int32_t* batt_node;  /* [n_batt] */
+  const double* eta_min;     /* [n_gens + n_lines + n_batt], >= 0 */
+  const double* eta_max;     /* [n_gens + n_lines + n_batt], >= eta_min */
+} gp_network;
+
+/* One operating scenario (Section 2.1: each scenario s has its own cost and
+ * constraints; Section 3 uses independent days). */
+typedef struct {
+  int32_t network;     /* index into gp_case_desc.networks */
+  int32_t T;           /* hours, 1 <= T <= 8784 */
+  const float* avail;  /* [n_gens * T], availability in [0, 1], [g][t] */
+  const float* load;   /* [n_nodes * T], MW, >= 0, [n][t] */
+  double weight;       /* w_s, scales h_s in the planner objective */
+} gp_scenario;
+
+typedef struct {
+  int32_t n_networks;
+  const gp_network* networks;
+  int32_t n_scenarios;
+  const gp_scenario* scenarios;
+  double r;         /* quadratic regulariser, $/MW^2 h, > 0 */
+  double lambda_u;  /* unserved-load penalty, $/MWh, > 0 */
+  double eff;       /* charging efficiency in (0, 1] */
+  double hours;     /* battery duration, h, > 0 */
+} gp_case_desc;
+
+/* Solver options.  Zero-initialise and set what you need; zero fields take
+ * the defaults given in brackets. */
+typedef struct {
+  double tol;            /* relative KKT residual target [1e-4] */
+  int32_t max_iter;      /* per solve [200000] */
+  int32_t check_every;   /* iterations between convergence checks [64] */
+  int32_t block;         /* threads per block; 0 = tuned table [0] */
+  int32_t no_graph;      /* 1 = launch eagerly instead of hipGraph replay */
+  double rho0;           /* initial primal weight [10] */
+  int32_t verbose;       /* 1 = progress lines on stderr */
+  int32_t reserved[7];
+} gp_options;
+
+/* Per-scenario solve statistics. */
+typedef struct {
+  int32_t iters;     /* iterations used */
+  int32_t restarts;  /* restarts taken */
+  int32_t status;    /* 0 converged, 1 iteration limit */
+  int32_t pad;
+  double r_pri, r_dual, r_gap, kkt;  /* relative KKT residual parts (FP64) */
+  double cost;       /* c_s(x) at the returned point */
+  double emis;       /* sum emis_g p at the returned point, t */
+  double primal_weight;  /* final primal weight */
+} gp_solve_stats;
+
+/* Build a plan: copies the case to device memory in the library's own
+ * layout.  hip_stream may be NULL: the plan then works on a private
+ * non-blocking stream of its own (every call synchronises it before
+ * returning).  On success *out owns
+ * device memory until plan_free.  Errors: GP_EINVAL (bad shapes, indices,
+ * NaN/Inf, negative costs or capacities), GP_ENOMEM, GP_EHIP. */
+int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void* hip_stream);
+
+/* Solve the dispatch map x*_s(eta) (eq. (2)) for the listed scenarios at the
+ * capacities eta (host FP64, [K], inside [eta_min, eta_max]) to the
+ * relative KKT residual opt.tol:
+ *   max(r_pri, r_dual, r_gap) with
+ *   r_pri = ||E x - e||_inf / (1 + ||e||_inf),
+ *   r_dual = ||(E'y - q - r x)_free||_inf / (1 + ||q||_inf),
+ *   r_gap = |P(x) - D(y)| / (1 + max(|P(x)|, |D(y)|)), D the exact dual
+ *   function, all in FP64.
+ * scen: [nb] distinct scenario indices.  warm_mode: 0 cold start, 1 start
+ * from each scenario's last solution.  cost_out: [nb] c_s(x) (nullable).
+ * stats_out: [nb] (nullable).  Returns GP_OK, GP_ENOTCONVERGED or an error. */
+int dispatch_solve_batch(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb,
+                         int32_t warm_mode, double* cost_out, gp_solve_stats* stats_out);
+
+/* Implicit gradient (Section 2.2) of the weighted mean planner objective
+ *   (1/nb) sum_s w_s h_s(x*_s(eta)),  h_s = c_s + omega * emissions,
+ * with respect to eta, for the scenarios of the last dispatch_solve_batch
+ * call (scen must equal that list).  The gamma term is not included.
+ * grad_out: [K] host FP64.  h_out: nullable, receives the weighted mean
+ * planner objective.  Errors: GP_ESTATE when no matching solve exists. */
+int dispatch_grad(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,
+                  double* h_out);
+
+/* One projected gradient step (Section 2.2):
+ *   Delta = gamma + dispatch_grad(...),  eta <- clip(eta - alpha*Delta).
+ * Solves the listed scenarios (a stochastic batch when nb < S) at eta_inout,
+ * warm-started from their previous solutions when warm_mode = 1.
+ * gamma: [K] $/MW-yr.  eta_inout: [K] updated in place.  phi_out: nullable,
+ * receives gamma'eta + (1/nb) sum w_s h_s at the input eta.
+ * delta_out: nullable [K], receives Delta. */
+int plan_step(gp_plan* p, double alpha, const int32_t* scen, int32_t nb, const double* gamma,
+              double omega, int32_t warm_mode, double* eta_inout, double* phi_out,
+              double* delta_out);
+
+/* Copy scenario s's last solution (canonical orders above) to host buffers:
+ * x_out [n_x] FP32 and y_out [n_y] FP64 (either nullable).  n_x and n_y are
+ * returned through the nullable size pointers. */
+int dispatch_get_solution(gp_plan* p, int32_t s, float* x_out, double* y_out, int64_t* n_x,
+                          int64_t* n_y);
+
+/* Replace scenario s's starting point for the next warm_mode = 1 solve
+ * (canonical orders; host x FP32 [n_x], y FP64 [n_y]; y may be NULL to keep
+ * the stored dual, or zeros when there is none). */
+int dispatch_set_start(gp_plan* p, int32_t s, const float* x, const double* y);
+
+/* Measurement aid: continue the last solve of the listed scenarios (scen
+ * must equal that call's list) for `iters` iterations launched eagerly and
+ * return the mean duration, in ms from HIP events on the plan's stream, of
+ * one launch of the row (dual) sweep and of the variable (primal) sweep.
+ * Leaves the stored solutions untouched. */
+int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters, double* ms_dual,
+                     double* ms_primal);
+
+/* Number of capacities K and scenarios S of a plan. */
+int plan_sizes(const gp_plan* p, int64_t* K, int32_t* S);
+
+/* Free the plan and its device memory (NULL is ignored). */
+void plan_free(gp_plan* p);
+
+/* Message for the last error on this plan (or of the last failed plan_init
+ * when p is NULL); never NULL. */
+const char* plan_last_error(const gp_plan* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDPLAN_H */

@@ -1,0 +1,772 @@
+// HIP kernels of the batched dispatch solver (gfx950).
+//
+// The solver is a consensus ADMM on the dispatch QP of each scenario: every
+// variable that appears in several equality blocks (nodal balance rows, DC
+// flow rows, battery state-of-charge chains) gets one copy per block, the
+// variable block carries the cost and the box, and the copy block projects
+// onto the equalities.  Eliminating the copies leaves one scalar dual per
+// equality row and the iteration becomes a preconditioned primal-dual step:
+//   y^ = y - c S (E x - e)                 S block-exact: 1/||row||^2 for
+//                                          balance and flow rows, a
+//                                          circulant inverse per battery chain
+//   x^ = clip((c rho x + E'(2y^ - y) - q) / (r + c rho), lo, hi)
+// wrapped in a reflected Halpern iteration with an anchor (x0, y0) that the
+// host moves at adaptive restarts.  c is a per-scenario primal weight.
+//
+// All sweeps are memory-bound: no dense contraction appears, so nothing uses
+// MFMA.  Every array is [device][hour] per scenario, so consecutive lanes
+// walk consecutive hours of one device and every gather of a node or line
+// dual is a contiguous run of hours.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "gp_device.h"
+
+namespace gp {
+
+#define GP_INF __builtin_huge_valf()
+
+// Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
+// contiguous range of tiles so that the gathers of one scenario's duals hit
+// the same L2.
+__device__ __forceinline__ int remap_xcd(int bid, int nblk) {
+  constexpr int X = 8;
+  const int per = nblk / X, rem = nblk % X;
+  const int xcd = bid % X, j = bid / X;
+  return xcd * per + min(xcd, rem) + j;
+}
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi) {
+  return fminf(fmaxf(v, lo), hi);
+}
+
+// ----------------------------------------------------------------------------
+// dual (row) sweep
+// ----------------------------------------------------------------------------
+
+// residual of balance row (n, t) for the primal vector xs of one scenario
+__device__ __forceinline__ float bal_residual(const Args& a, const NetDev& nt, const float* xs,
+                                              int T, int n, int t, float load) {
+  const int64_t TT = T;
+  float res = xs[(int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + (int64_t)n * TT + t] - load;
+  const int e0 = a.term_ptr[nt.tptr_off + n], e1 = a.term_ptr[nt.tptr_off + n + 1];
+  const float* pf = xs + (int64_t)nt.G * TT;
+  const float* pch = xs + (int64_t)(nt.G + nt.L + nt.N) * TT;
+  const float* pdis = pch + (int64_t)nt.B * TT;
+  for (int e = e0; e < e1; ++e) {
+    const int code = a.term[e];
+    const int idx = code >> 2;
+    switch (code & 3) {
+      case TT_GEN: res += xs[(int64_t)idx * TT + t]; break;
+      case TT_BATT: res += pdis[(int64_t)idx * TT + t] - pch[(int64_t)idx * TT + t]; break;
+      case TT_LINE_TO: res += pf[(int64_t)idx * TT + t]; break;
+      default: res -= pf[(int64_t)idx * TT + t]; break;
+    }
+  }
+  return res;
+}
+
+__device__ __forceinline__ float flow_residual(const Args& a, const NetDev& nt, const float* xs,
+                                               int T, int l, int t) {
+  const int64_t TT = T;
+  const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+  const float b = a.line_beta[nt.line_off + l];
+  const float* th = xs + (int64_t)(nt.G + nt.L) * TT;
+  return xs[(int64_t)nt.G * TT + (int64_t)l * TT + t] - b * (th[(int64_t)fr * TT + t] - th[(int64_t)to * TT + t]);
+}
+
+__device__ __forceinline__ float soc_residual(const NetDev& nt, const float* xs, int T, int k, int t,
+                                              float eff) {
+  const int64_t TT = T;
+  const float* pch = xs + (int64_t)(nt.G + nt.L + nt.N) * TT + (int64_t)k * TT;
+  const float* pdis = pch + (int64_t)nt.B * TT;
+  const float* psoc = pdis + (int64_t)nt.B * TT;
+  const int tp = (t == 0) ? T - 1 : t - 1;
+  return psoc[t] - psoc[tp] - eff * pch[t] + pdis[t];
+}
+
+__device__ __forceinline__ void dual_update(const Args& a, int64_t row, double step, double lam,
+                                            int check) {
+  const double yv = a.y[row];
+  const double yh = yv - step;
+  const double e2 = 2.0 * yh - yv;
+  a.ybar[row] = e2;
+  a.y[row] = lam * e2 + (1.0 - lam) * a.y0[row];
+  if (check) a.yhat[row] = yh;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_dual(Args a, int j, int check) {
+  const int tix = remap_xcd(blockIdx.x, gridDim.x);
+  const Tile tl = a.rtiles[tix];
+  const int s = tl.scen;
+  if (!a.active[s]) return;
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int T = sc.T;
+  const int64_t TT = T;
+  const double c = a.cw[s];
+  const int k = a.kbase[s] + j;
+  const double lam = (double)(k + 1) / (double)(k + 2);
+  const float* xs = a.x + sc.xoff;
+  if (tl.cls == RC_SOC) {
+    // one battery chain per block: residuals to LDS, then the circulant
+    // inverse of the chain block (C R^-1 C') applied as a short convolution
+    extern __shared__ float sres[];
+    const int kb = tl.start;
+    for (int t = threadIdx.x; t < T; t += BS) sres[t] = soc_residual(nt, xs, T, kb, t, a.eff);
+    __syncthreads();
+    const float* h = a.taps + sc.tap_off;
+    const int J = sc.ntap - 1;
+    const int64_t rbase = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)kb * TT;
+    for (int t = threadIdx.x; t < T; t += BS) {
+      float acc;
+      if (2 * J + 1 >= T) {
+        acc = 0.f;
+        int tt = t;
+        for (int jj = 0; jj < T; ++jj) {
+          acc += h[jj] * sres[tt];
+          tt = (tt + 1 == T) ? 0 : tt + 1;
+        }
+      } else {
+        acc = h[0] * sres[t];
+        for (int jj = 1; jj <= J; ++jj) {
+          int tp = t + jj;
+          if (tp >= T) tp -= T;
+          int tm = t - jj;
+          if (tm < 0) tm += T;
+          acc += h[jj] * (sres[tp] + sres[tm]);
+        }
+      }
+      dual_update(a, rbase + t, c * (double)acc, lam, check);
+    }
+    return;
+  }
+  const int li = threadIdx.x;
+  if (li >= tl.count) return;
+  const int i = tl.start + li;
+  if (tl.cls == RC_BAL) {
+    const int n = i / T, t = i - n * T;
+    const float load = a.mode ? 0.f : a.load[sc.doff + i];
+    const float res = bal_residual(a, nt, xs, T, n, t, load);
+    dual_update(a, sc.yoff + i, c * (double)a.sig_bal[nt.node_off + n] * (double)res, lam, check);
+  } else {  // RC_FLOW
+    const int l = i / T, t = i - l * T;
+    const float res = flow_residual(a, nt, xs, T, l, t);
+    dual_update(a, sc.yoff + (int64_t)nt.N * TT + i, c * (double)a.cwf[s] * (double)a.w.sig_flow * (double)res,
+                lam, check);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// primal (variable) sweep
+// ----------------------------------------------------------------------------
+
+struct Upd {
+  float* x;
+  const float* x0;
+  float* xh;
+  const uint8_t* am;
+  float c, lam, r;
+  int check, mode;
+  // E'y - q is formed in FP64 (prices near the unserved-load penalty
+  // minus that penalty); the proximal step and the Halpern update in FP32
+  __device__ __forceinline__ void operator()(int64_t idx, double ey, float q, float rho, float lo,
+                                             float hi) const {
+    if (mode) {  // adjoint: active entries are fixed at 0, the rest are free
+      const bool fix = am[idx] != 0;
+      lo = fix ? 0.f : -GP_INF;
+      hi = fix ? 0.f : GP_INF;
+    }
+    const float xv = x[idx];
+    const float cr = c * rho;
+    const float g = (float)(ey - (double)q);
+    const float v = clampf((cr * xv + g) / (r + cr), lo, hi);
+    x[idx] = lam * (2.f * v - xv) + (1.f - lam) * x0[idx];
+    if (check) xh[idx] = v;
+  }
+};
+
+// E'y for the angle of node n at hour t: sum over incident lines of
+// (+beta if the node is the line's 'to' end, -beta if 'from') * mu
+__device__ __forceinline__ double angle_ety(const Args& a, const NetDev& nt, const double* yf, int T,
+                                            int n, int t) {
+  const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
+  double ey = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int code = a.ang[e];
+    const int l = code >> 1;
+    const double bv = (double)a.line_beta[nt.line_off + l] * yf[(int64_t)l * T + t];
+    ey += (code & 1) ? -bv : bv;
+  }
+  return ey;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_primal(Args a, int j, int check) {
+  const int tix = remap_xcd(blockIdx.x, gridDim.x);
+  const Tile tl = a.vtiles[tix];
+  const int s = tl.scen;
+  if (!a.active[s]) return;
+  const int li = threadIdx.x;
+  if (li >= tl.count) return;
+  const int i = tl.start + li;
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int T = sc.T;
+  const int64_t TT = T;
+  const int k = a.kbase[s] + j;
+  Upd u{a.x + sc.xoff, a.x0 + sc.xoff, a.xhat + sc.xoff, a.amask ? a.amask + sc.xoff : nullptr,
+        a.cw[s], (float)(k + 1) / (float)(k + 2), a.r, check, a.mode};
+  const double* yb = a.ybar + sc.yoff;
+  const double* yf = yb + (int64_t)nt.N * TT;
+  const double* ys = yf + (int64_t)nt.L * TT;
+  switch (tl.cls) {
+    case VC_GEN: {
+      const int g = i / T, t = i - g * T;
+      const int n = a.gen_node[nt.gen_off + g];
+      const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
+      const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
+      u(i, yb[(int64_t)n * TT + t], q, a.w.wb, 0.f, hi);
+      break;
+    }
+    case VC_LINE: {
+      const int l = i / T, t = i - l * T;
+      const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+      const double ey = yb[(int64_t)to * TT + t] - yb[(int64_t)fr * TT + t] + yf[i];
+      const float cap = a.eta[nt.eta_off + nt.G + l];
+      u((int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + a.cwf[s] * a.w.wf, -cap, cap);
+      break;
+    }
+    case VC_NODE: {
+      const int n = i / T, t = i - n * T;
+      const double ey = angle_ety(a, nt, yf, T, n, t);
+      u((int64_t)(nt.G + nt.L) * TT + i, ey, 0.f, a.cwf[s] * a.rho_th[nt.node_off + n], -GP_INF, GP_INF);
+      u((int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i, yb[i], a.mode ? 0.f : a.lambda_u,
+        a.w.wu, 0.f, GP_INF);
+      break;
+    }
+    default: {  // VC_BATT
+      const int kb = i / T, t = i - kb * T;
+      const int n = a.batt_node[nt.batt_off + kb];
+      const double pb = yb[(int64_t)n * TT + t];
+      const double nu = ys[i];
+      const double nu1 = ys[(int64_t)kb * TT + ((t + 1 == T) ? 0 : t + 1)];
+      const float cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
+      const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+      const int64_t BT = (int64_t)nt.B * TT;
+      u(base + i, -pb - (double)a.eff * nu, 0.f, a.w.rho_b, 0.f, cap);
+      u(base + BT + i, pb + nu, 0.f, a.w.rho_b, 0.f, cap);
+      u(base + 2 * BT + i, nu - nu1, 0.f, a.w.ws, 0.f, a.hours * cap);
+      break;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// convergence statistics (FP64)
+// ----------------------------------------------------------------------------
+
+template <int BS>
+__device__ __forceinline__ void block_reduce_store(double (&v)[kStats], double* out) {
+  // wavefront reduce then LDS across wavefronts; slots below kMaxStats are maxima
+  constexpr int W = 64;
+  constexpr int NW = BS / W;
+  __shared__ double sh[NW][kStats];
+#pragma unroll
+  for (int q = 0; q < kStats; ++q) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v[q], o, W);
+      v[q] = (q < kMaxStats) ? fmax(v[q], ov) : v[q] + ov;
+    }
+  }
+  const int lane = threadIdx.x % W, wid = threadIdx.x / W;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kStats; ++q) sh[wid][q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < kStats) {
+    const int q = threadIdx.x;
+    double acc = sh[0][q];
+    for (int w = 1; w < NW; ++w) acc = (q < kMaxStats) ? fmax(acc, sh[w][q]) : acc + sh[w][q];
+    out[q] = acc;
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_check_rows(Args a) {
+  const int tix = blockIdx.x;
+  const Tile tl = a.rtiles[tix];
+  const int s = tl.scen;
+  double v[kStats];
+#pragma unroll
+  for (int q = 0; q < kStats; ++q) v[q] = 0.0;
+  if (a.active[s]) {
+    const ScenDev sc = a.scen[s];
+    const NetDev nt = a.net[sc.net];
+    const int T = sc.T;
+    const int64_t TT = T;
+    const float* xs = a.xhat + sc.xoff;
+    const float c = a.cw[s];
+    if (tl.cls == RC_SOC) {
+      const int kb = tl.start;
+      const float dg = (3.f + a.eff * a.eff) / a.w.ws;
+      const int64_t rbase = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)kb * TT;
+      for (int t = threadIdx.x; t < T; t += BS) {
+        const double res = soc_residual(nt, xs, T, kb, t, a.eff);
+        const double dy = (double)a.yhat[rbase + t] - (double)a.y0[rbase + t];
+        v[ST_RESS_MAX] = fmax(v[ST_RESS_MAX], fabs(res));
+        v[ST_DY2] += dg * dy * dy;
+      }
+    } else if ((int)threadIdx.x < tl.count) {
+      const int i = tl.start + threadIdx.x;
+      double res, den;
+      int64_t row;
+      int slot = ST_RES_MAX;
+      if (tl.cls == RC_BAL) {
+        const int n = i / T, t = i - n * T;
+        const float load = a.mode ? 0.f : a.load[sc.doff + i];
+        res = bal_residual(a, nt, xs, T, n, t, load);
+        den = 1.0 / a.sig_bal[nt.node_off + n];
+        row = sc.yoff + i;
+        v[ST_D] += (double)load * (double)a.yhat[row];
+      } else {
+        const int l = i / T, t = i - l * T;
+        res = flow_residual(a, nt, xs, T, l, t);
+        den = 1.0 / ((double)a.cwf[s] * a.w.sig_flow);
+        row = sc.yoff + (int64_t)nt.N * TT + i;
+        slot = ST_RESF_MAX;
+      }
+      const double dy = (double)a.yhat[row] - (double)a.y0[row];
+      v[slot] = fabs(res);
+      v[ST_DY2] = den * dy * dy;
+    }
+    (void)c;
+  }
+  block_reduce_store<BS>(v, a.part_r + (int64_t)tix * kStats);
+}
+
+// contribution of one variable to the statistics: objective, exact dual
+// function (Lagrangian minimiser in closed form), stationarity of free
+// entries, distance to the anchor
+__device__ __forceinline__ void var_stats(double (&v)[kStats], double x, double x0, double ey,
+                                          double q, double r, double lo, double hi, double rho) {
+  v[ST_P] += 0.5 * r * x * x + q * x;
+  v[ST_XMAX] = fmax(v[ST_XMAX], fabs(x));
+  double xy = (ey - q) / r;
+  xy = fmin(fmax(xy, lo), hi);
+  v[ST_D] += q * xy + 0.5 * r * xy * xy - ey * xy;
+  if (lo == -HUGE_VAL && hi == HUGE_VAL) v[ST_DUAL_MAX] = fmax(v[ST_DUAL_MAX], fabs(ey - q - r * x));
+  const double dx = x - x0;
+  v[ST_DX2] += rho * dx * dx;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_check_vars(Args a) {
+  const int tix = blockIdx.x;
+  const Tile tl = a.vtiles[tix];
+  const int s = tl.scen;
+  double v[kStats];
+#pragma unroll
+  for (int q = 0; q < kStats; ++q) v[q] = 0.0;
+  if (a.active[s] && (int)threadIdx.x < tl.count) {
+    const ScenDev sc = a.scen[s];
+    const NetDev nt = a.net[sc.net];
+    const int T = sc.T;
+    const int64_t TT = T;
+    const int i = tl.start + threadIdx.x;
+    const float* xh = a.xhat + sc.xoff;
+    const float* x0 = a.x0 + sc.xoff;
+    const double* yb = a.yhat + sc.yoff;
+    const double* yf = yb + (int64_t)nt.N * TT;
+    const double* ys = yf + (int64_t)nt.L * TT;
+    const double r = a.r;
+    const double INF = HUGE_VAL;
+    const uint8_t* am = a.amask ? a.amask + sc.xoff : nullptr;
+    auto bnd = [&](int64_t idx, double& lo, double& hi) {
+      if (a.mode) {
+        const bool fix = am[idx] != 0;
+        lo = fix ? 0.0 : -INF;
+        hi = fix ? 0.0 : INF;
+      }
+    };
+    switch (tl.cls) {
+      case VC_GEN: {
+        const int g = i / T, t = i - g * T;
+        const int n = a.gen_node[nt.gen_off + g];
+        double lo = 0.0, hi = (double)(a.avail[sc.aoff + i] * a.eta[nt.eta_off + g]);
+        bnd(i, lo, hi);
+        const double cost = a.gen_cost[nt.gen_off + g], em = a.gen_emis[nt.gen_off + g];
+        const double q = a.mode ? (double)a.omega * em : cost;
+        const double xv = xh[i];
+        var_stats(v, xv, x0[i], yb[(int64_t)n * TT + t], q, r, lo, hi, a.w.wb);
+        v[ST_EMIS] += em * xv;
+        v[ST_FUEL] += cost * xv;
+        break;
+      }
+      case VC_LINE: {
+        const int l = i / T, t = i - l * T;
+        const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+        const double ey = (double)yb[(int64_t)to * TT + t] - (double)yb[(int64_t)fr * TT + t] + (double)yf[i];
+        const double cap = a.eta[nt.eta_off + nt.G + l];
+        const int64_t idx = (int64_t)nt.G * TT + i;
+        double lo = -cap, hi = cap;
+        bnd(idx, lo, hi);
+        var_stats(v, xh[idx], x0[idx], ey, 0.0, r, lo, hi, 2.0 * a.w.wb + (double)a.cwf[s] * a.w.wf);
+        break;
+      }
+      case VC_NODE: {
+        const int n = i / T, t = i - n * T;
+        // angle: E'y in FP64
+        const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
+        double ey = 0.0;
+        for (int e = e0; e < e1; ++e) {
+          const int code = a.ang[e];
+          const int l = code >> 1;
+          const double bv = (double)a.line_beta[nt.line_off + l] * (double)yf[(int64_t)l * TT + t];
+          ey += (code & 1) ? -bv : bv;
+        }
+        int64_t idx = (int64_t)(nt.G + nt.L) * TT + i;
+        double lo = -INF, hi = INF;
+        bnd(idx, lo, hi);
+        var_stats(v, xh[idx], x0[idx], ey, 0.0, r, lo, hi, (double)a.cwf[s] * a.rho_th[nt.node_off + n]);
+        idx = (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i;
+        lo = 0.0;
+        hi = INF;
+        bnd(idx, lo, hi);
+        var_stats(v, xh[idx], x0[idx], yb[i], a.mode ? 0.0 : (double)a.lambda_u, r, lo, hi, a.w.wu);
+        break;
+      }
+      default: {
+        const int kb = i / T, t = i - kb * T;
+        const int n = a.batt_node[nt.batt_off + kb];
+        const double pb = yb[(int64_t)n * TT + t];
+        const double nu = ys[i];
+        const double nu1 = ys[(int64_t)kb * TT + ((t + 1 == T) ? 0 : t + 1)];
+        const double cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
+        const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+        const int64_t BT = (int64_t)nt.B * TT;
+        const double eys[3] = {-pb - (double)a.eff * nu, pb + nu, nu - nu1};
+        const double his[3] = {cap, cap, (double)a.hours * cap};
+        const double rhos[3] = {a.w.rho_b, a.w.rho_b, a.w.ws};
+        for (int q3 = 0; q3 < 3; ++q3) {
+          const int64_t idx = base + q3 * BT + i;
+          double lo = 0.0, hi = his[q3];
+          bnd(idx, lo, hi);
+          var_stats(v, xh[idx], x0[idx], eys[q3], 0.0, r, lo, hi, rhos[q3]);
+        }
+        break;
+      }
+    }
+  }
+  block_reduce_store<BS>(v, a.part_v + (int64_t)tix * kStats);
+}
+
+// one block per batch entry: fold its tile partials in a fixed order
+template <int BS>
+__global__ __launch_bounds__(BS) void k_reduce(Args a) {
+  const int b = blockIdx.x;
+  const int s = a.bscen[b];
+  double v[kStats];
+#pragma unroll
+  for (int q = 0; q < kStats; ++q) v[q] = 0.0;
+  if (a.active[s]) {
+    const int v0 = a.ranges[4 * b], v1 = a.ranges[4 * b + 1];
+    const int r0 = a.ranges[4 * b + 2], r1 = a.ranges[4 * b + 3];
+    for (int t = v0 + threadIdx.x; t < v1; t += BS) {
+#pragma unroll
+      for (int q = 0; q < kStats; ++q) {
+        const double pv = a.part_v[(int64_t)t * kStats + q];
+        v[q] = (q < kMaxStats) ? fmax(v[q], pv) : v[q] + pv;
+      }
+    }
+    for (int t = r0 + threadIdx.x; t < r1; t += BS) {
+#pragma unroll
+      for (int q = 0; q < kStats; ++q) {
+        const double pv = a.part_r[(int64_t)t * kStats + q];
+        v[q] = (q < kMaxStats) ? fmax(v[q], pv) : v[q] + pv;
+      }
+    }
+  }
+  __syncthreads();
+  block_reduce_store<BS>(v, a.stats + (int64_t)b * kStats);
+}
+
+// ----------------------------------------------------------------------------
+// state reset / restart
+// ----------------------------------------------------------------------------
+
+// mode 0: cold start (zeros), 1: restart from (xhat, yhat) where restart[s]
+template <int BS>
+__global__ __launch_bounds__(BS) void k_reset(Args a, int cold) {
+  const bool rows = (int)blockIdx.x >= a.nvt;
+  const int tix = rows ? (int)blockIdx.x - a.nvt : (int)blockIdx.x;
+  const Tile tl = rows ? a.rtiles[tix] : a.vtiles[tix];
+  const int s = tl.scen;
+  if (!a.restart[s]) return;
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int T = sc.T;
+  const int64_t TT = T;
+  if (!rows) {
+    if ((int)threadIdx.x >= tl.count) return;
+    const int i = tl.start + threadIdx.x;
+    int64_t idx[3];
+    int nidx = 1;
+    switch (tl.cls) {
+      case VC_GEN: idx[0] = i; break;
+      case VC_LINE: idx[0] = (int64_t)nt.G * TT + i; break;
+      case VC_NODE:
+        idx[0] = (int64_t)(nt.G + nt.L) * TT + i;
+        idx[1] = (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i;
+        nidx = 2;
+        break;
+      default: {
+        const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+        const int64_t BT = (int64_t)nt.B * TT;
+        idx[0] = base + i;
+        idx[1] = base + BT + i;
+        idx[2] = base + 2 * BT + i;
+        nidx = 3;
+      }
+    }
+    for (int q = 0; q < nidx; ++q) {
+      const int64_t g = sc.xoff + idx[q];
+      const float v = cold ? 0.f : a.xhat[g];
+      a.x[g] = v;
+      a.x0[g] = v;
+      a.xhat[g] = v;
+    }
+  } else {
+    if (tl.cls == RC_SOC) {
+      const int64_t rbase = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)tl.start * TT;
+      for (int t = threadIdx.x; t < T; t += BS) {
+        const double v = cold ? 0.0 : a.yhat[rbase + t];
+        a.y[rbase + t] = v;
+        a.y0[rbase + t] = v;
+        a.ybar[rbase + t] = v;
+        a.yhat[rbase + t] = v;
+      }
+      return;
+    }
+    if ((int)threadIdx.x >= tl.count) return;
+    const int i = tl.start + threadIdx.x;
+    const int64_t g = sc.yoff + (tl.cls == RC_BAL ? (int64_t)i : (int64_t)nt.N * TT + i);
+    const double v = cold ? 0.0 : a.yhat[g];
+    a.y[g] = v;
+    a.y0[g] = v;
+    a.ybar[g] = v;
+    a.yhat[g] = v;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// capacity gradient: envelope pass over the active bounds
+// ----------------------------------------------------------------------------
+
+// For every device of every batch scenario, sum over hours of a_i * (-z_i)
+// over entries at a capacity-dependent bound, z = E'y - q - r x evaluated at
+// (xhat, yhat).  One wavefront per device (lanes over hours), FP64.  In
+// adjoint mode the same pass runs on the adjoint solution with the mask of
+// the forward solve.  out: [batch][K_net] at goff[b].
+template <int BS>
+__global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb, int mode_adj) {
+  constexpr int W = 64;
+  const int wid = (blockIdx.x * BS + threadIdx.x) / W;
+  const int lane = threadIdx.x % W;
+  // wavefront wid -> (batch entry, device) via a linear scan over entries
+  int b = 0;
+  int64_t base = 0;
+  int dev = -1;
+  for (; b < nb; ++b) {
+    const int s = a.bscen[b];
+    const NetDev nt = a.net[a.scen[s].net];
+    const int Kn = nt.G + nt.L + nt.B;
+    if (wid < base + Kn) {
+      dev = (int)(wid - base);
+      break;
+    }
+    base += Kn;
+  }
+  if (dev < 0) return;
+  const int s = a.bscen[b];
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int T = sc.T;
+  const int64_t TT = T;
+  const float* xh = a.xhat + sc.xoff;
+  const double* yb = a.yhat + sc.yoff;
+  const double* yf = yb + (int64_t)nt.N * TT;
+  const double* ys = yf + (int64_t)nt.L * TT;
+  const uint8_t* am = a.amask + sc.xoff;  // 1 at lower, 2 at upper bound (forward solve)
+  const double r = a.r;
+  double acc = 0.0;
+  if (dev < nt.G) {
+    const int g = dev;
+    const int n = a.gen_node[nt.gen_off + g];
+    const double q = mode_adj ? (double)a.omega * a.gen_emis[nt.gen_off + g] : (double)a.gen_cost[nt.gen_off + g];
+    for (int t = lane; t < T; t += W) {
+      const int64_t idx = (int64_t)g * TT + t;
+      if (am[idx] & 2) {
+        const double z = (double)yb[(int64_t)n * TT + t] - q - r * (double)xh[idx];
+        acc += (double)a.avail[sc.aoff + idx] * (-z);
+      }
+    }
+  } else if (dev < nt.G + nt.L) {
+    const int l = dev - nt.G;
+    const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+    for (int t = lane; t < T; t += W) {
+      const int64_t idx = (int64_t)nt.G * TT + (int64_t)l * TT + t;
+      const uint8_t m = am[idx];
+      if (m) {
+        const double z = (double)yb[(int64_t)to * TT + t] - (double)yb[(int64_t)fr * TT + t] +
+                         (double)yf[(int64_t)l * TT + t] - r * (double)xh[idx];
+        acc += (m & 2) ? -z : z;
+      }
+    }
+  } else {
+    const int kb = dev - nt.G - nt.L;
+    const int n = a.batt_node[nt.batt_off + kb];
+    const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+    const int64_t BT = (int64_t)nt.B * TT;
+    for (int t = lane; t < T; t += W) {
+      const double pb = yb[(int64_t)n * TT + t];
+      const double nu = ys[(int64_t)kb * TT + t];
+      const double nu1 = ys[(int64_t)kb * TT + ((t + 1 == T) ? 0 : t + 1)];
+      const int64_t i0 = base + (int64_t)kb * TT + t;
+      if (am[i0] & 2) acc += -((-pb - (double)a.eff * nu) - r * (double)xh[i0]);
+      if (am[i0 + BT] & 2) acc += -((pb + nu) - r * (double)xh[i0 + BT]);
+      if (am[i0 + 2 * BT] & 2) acc += (double)a.hours * -((nu - nu1) - r * (double)xh[i0 + 2 * BT]);
+    }
+  }
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
+  if (lane == 0) a.stats[goff[b] + dev] = acc;  // stats buffer reused as gradient output
+}
+
+// Active-bound mask of the forward solution: bit 0 = at lower bound, bit 1
+// = at an upper bound that depends on a capacity.  Entries whose two bounds
+// coincide (zero availability) are marked at their lower bound only.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
+  const int tix = blockIdx.x;
+  const Tile tl = a.vtiles[tix];
+  if ((int)threadIdx.x >= tl.count) return;
+  const int s = tl.scen;
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int T = sc.T;
+  const int64_t TT = T;
+  const int i = tl.start + threadIdx.x;
+  const float* xh = a.xhat + sc.xoff;
+  uint8_t* m = mask + sc.xoff;
+  auto mk = [&](int64_t idx, float lo, float hi, bool hi_dep, bool lo_dep) {
+    const float v = xh[idx];
+    uint8_t b = 0;
+    if (v <= lo) b |= 1;
+    if (v >= hi && hi > lo) b |= hi_dep ? 2 : 1;
+    (void)lo_dep;
+    m[idx] = b;
+  };
+  switch (tl.cls) {
+    case VC_GEN: {
+      const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + i / T];
+      mk(i, 0.f, hi, true, false);
+      break;
+    }
+    case VC_LINE: {
+      const int l = i / T;
+      const float cap = a.eta[nt.eta_off + nt.G + l];
+      const int64_t idx = (int64_t)nt.G * TT + i;
+      const float v = xh[idx];
+      uint8_t b = 0;
+      if (cap > 0.f) {
+        if (v >= cap) b = 2;
+        else if (v <= -cap) b = 1;
+      } else {
+        b = 1;
+      }
+      m[idx] = b;
+      break;
+    }
+    case VC_NODE: {
+      m[(int64_t)(nt.G + nt.L) * TT + i] = 0;
+      const int64_t iu = (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i;
+      m[iu] = xh[iu] <= 0.f ? 1 : 0;
+      break;
+    }
+    default: {
+      const int kb = i / T;
+      const float cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
+      const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+      const int64_t BT = (int64_t)nt.B * TT;
+      mk(base + i, 0.f, cap, true, false);
+      mk(base + BT + i, 0.f, cap, true, false);
+      mk(base + 2 * BT + i, 0.f, a.hours * cap, true, false);
+      break;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host-callable launchers (block size is a template parameter)
+// ----------------------------------------------------------------------------
+
+#define GP_DISPATCH_BS(bs, call) \
+  switch (bs) {                  \
+    case 64: call(64); break;    \
+    case 128: call(128); break;  \
+    case 512: call(512); break;  \
+    default: call(256); break;   \
+  }
+
+hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st) {
+  const size_t sh = (size_t)max_T * sizeof(float);
+#define L_(B) hipLaunchKernelGGL(k_dual<B>, dim3(a.nrt), dim3(B), sh, st, a, j, check)
+  GP_DISPATCH_BS(bs, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st) {
+#define L_(B) hipLaunchKernelGGL(k_primal<B>, dim3(a.nvt), dim3(B), 0, st, a, j, check)
+  GP_DISPATCH_BS(bs, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st) {
+#define L_(B)                                                                  \
+  hipLaunchKernelGGL(k_check_rows<B>, dim3(a.nrt), dim3(B), 0, st, a);         \
+  hipLaunchKernelGGL(k_check_vars<B>, dim3(a.nvt), dim3(B), 0, st, a);         \
+  hipLaunchKernelGGL(k_reduce<256>, dim3(nb), dim3(256), 0, st, a)
+  GP_DISPATCH_BS(bs, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(const Args& a, int bs, int cold, hipStream_t st) {
+#define L_(B) hipLaunchKernelGGL(k_reset<B>, dim3(a.nvt + a.nrt), dim3(B), 0, st, a, cold)
+  GP_DISPATCH_BS(bs, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st) {
+#define L_(B) hipLaunchKernelGGL(k_mask<B>, dim3(a.nvt), dim3(B), 0, st, a, mask)
+  GP_DISPATCH_BS(bs, L_)
+#undef L_
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj,
+                       hipStream_t st) {
+  const int64_t threads = ndev * 64;
+  const int nblk = (int)((threads + 255) / 256);
+  hipLaunchKernelGGL(k_grad<256>, dim3(nblk), dim3(256), 0, st, a, goff, nb, mode_adj);
+  return hipGetLastError();
+}
+
+}  // namespace gp

@@ -1,0 +1,1183 @@
+// Host side of libgridplan: argument validation, device layout, the
+// restarted Halpern primal-dual driver (convergence checks, restarts,
+// primal-weight adaptation), hipGraph capture of iteration chunks, the
+// capacity gradient and the projected planning step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/gridplan.h"
+#include "gp_device.h"
+
+namespace gp {
+hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st);
+hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st);
+hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st);
+hipError_t launch_reset(const Args& a, int bs, int cold, hipStream_t st);
+hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st);
+hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj,
+                       hipStream_t st);
+}  // namespace gp
+
+using namespace gp;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct GpError {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw GpError{code, buf};
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) fail(GP_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      fail(e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EHIP, "hipMalloc of %zu bytes failed: %s",
+           count * sizeof(T), hipGetErrorString(e));
+    }
+  }
+  void upload(const std::vector<T>& v, hipStream_t st) {
+    alloc(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+template <class T>
+struct PinBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    hipError_t e = hipHostMalloc((void**)&p, count * sizeof(T), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      fail(GP_ENOMEM, "hipHostMalloc of %zu bytes failed", count * sizeof(T));
+    }
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  T& operator[](size_t i) { return p[i]; }
+  const T& operator[](size_t i) const { return p[i]; }
+  ~PinBuf() { release(); }
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+struct NetHost {
+  int N, L, G, B;
+  int64_t eta_off;  // global capacity offset
+  std::vector<double> eta_min, eta_max;
+};
+
+struct ScenHost {
+  int net, T;
+  double weight;
+  double einf;  // ||load||_inf
+  int64_t xoff, yoff, nx, ny;
+};
+
+}  // namespace
+
+// Restart and weight-adaptation parameters of the driver.  The defaults
+// were chosen by measurement; GP_* environment variables override them for
+// experiments.
+struct Tune {
+  double bsuff = 0.2;     // restart when the KKT residual fell by this factor
+  double bnec = 0.8;      // ... or by this factor and stopped improving
+  double art = 0.36;      // ... or the cycle is this fraction of all iterations
+  double pw_theta = 0.5;  // smoothing of the primal-weight update
+  int rule = 0;           // 0: balance weighted primal/dual movement; 1: balance residuals
+  int flow_rule = 0;      // 1: adapt the flow-class multiplier at restarts
+  double clamp = 10.0;    // largest factor of one weight update
+};
+
+double env_or(const char* k, double v) {
+  const char* e = std::getenv(k);
+  return e ? std::atof(e) : v;
+}
+
+struct gp_plan {
+  int trace = 0;  // GRIDPLAN_TRACE=1: per-check line for the first batch entry
+  Tune tune;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  gp_options opt{};
+  int S = 0;
+  int64_t K = 0;
+  double r = 0, lambda_u = 0, eff = 0, hours = 0, qinf = 0;
+  std::vector<NetHost> nets;
+  std::vector<ScenHost> scen;
+  int max_T = 1;
+  int64_t nx_tot = 0, ny_tot = 0;
+  Weights w{};
+
+  // device data
+  DevBuf<ScenDev> d_scen;
+  DevBuf<NetDev> d_net;
+  DevBuf<int32_t> d_gen_node, d_line_from, d_line_to, d_batt_node, d_term_ptr, d_term, d_ang_ptr,
+      d_ang;
+  DevBuf<float> d_gen_cost, d_gen_emis, d_line_beta, d_sig_bal, d_rho_th, d_taps, d_avail, d_load,
+      d_eta;
+  DevBuf<float> d_x, d_x0, d_xhat;
+  DevBuf<double> d_y, d_y0, d_ybar, d_yhat;
+  DevBuf<uint8_t> d_mask;
+  // adjoint state (allocated on first use)
+  DevBuf<float> a_x, a_x0, a_xhat;
+  DevBuf<double> a_y, a_y0, a_ybar, a_yhat;
+  // per-scenario control
+  DevBuf<float> d_cw, d_cwf;
+  DevBuf<int32_t> d_kbase, d_active, d_restart;
+  PinBuf<float> h_cw, h_cwf;
+  PinBuf<int32_t> h_kbase, h_active, h_restart;
+  // batch geometry
+  std::vector<int> batch;  // scenarios of the current tile tables
+  DevBuf<Tile> d_vt, d_rt;
+  int nvt = 0, nrt = 0;
+  DevBuf<int32_t> d_ranges, d_bscen;
+  DevBuf<double> d_part_v, d_part_r, d_stats;
+  PinBuf<double> h_stats;
+  DevBuf<double> d_gpart;
+  DevBuf<int64_t> d_goff;
+  PinBuf<double> h_gpart;
+  int64_t gpart_n = 0;
+  // graph of one iteration chunk
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_mode = -1;
+  // solution bookkeeping
+  std::vector<int> has_solution;
+  std::vector<float> last_cw, last_cwf;
+  std::vector<int> solved_batch;
+  std::vector<float> eta_f;  // capacities of the last solve
+  std::vector<double> eta_last;
+
+  ~gp_plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+int block_size(const gp_plan* p) { return p->opt.block > 0 ? p->opt.block : 256; }
+
+// SOC chain block (C R^-1 C') of one battery is circulant with diagonal
+// (3 + eff^2)/ws and off-diagonals -1/ws (cyclic); its inverse is circulant
+// too.  h_j = (1/T) sum_m cos(2 pi m j / T) / lambda_m with the eigenvalues
+// lambda_m = d + 2 o cos(2 pi m / T).
+std::vector<double> chain_inverse(int T, double eff, double ws) {
+  const double d = (3.0 + eff * eff) / ws, o = -1.0 / ws;
+  std::vector<double> lam(T), h(T, 0.0);
+  for (int m = 0; m < T; ++m) lam[m] = d + 2.0 * o * std::cos(2.0 * M_PI * m / T);
+  if (T == 1) lam[0] = (1.0 + eff * eff) / ws;  // soc terms cancel in a 1-hour cycle
+  for (int j = 0; j < T; ++j) {
+    double acc = 0.0;
+    for (int m = 0; m < T; ++m) acc += std::cos(2.0 * M_PI * (double)m * j / T) / lam[m];
+    h[j] = acc / T;
+  }
+  return h;
+}
+
+void validate_case(const gp_case_desc* cs) {
+  if (!cs) fail(GP_EINVAL, "case descriptor is NULL");
+  if (cs->n_networks < 1 || !cs->networks) fail(GP_EINVAL, "need at least one network");
+  if (cs->n_scenarios < 1 || !cs->scenarios) fail(GP_EINVAL, "need at least one scenario");
+  if (!(cs->r > 0) || !finite(cs->r)) fail(GP_EINVAL, "regulariser r must be > 0");
+  if (!(cs->lambda_u > 0) || !finite(cs->lambda_u)) fail(GP_EINVAL, "lambda_u must be > 0");
+  if (!(cs->eff > 0 && cs->eff <= 1)) fail(GP_EINVAL, "eff must be in (0, 1]");
+  if (!(cs->hours > 0) || !finite(cs->hours)) fail(GP_EINVAL, "hours must be > 0");
+  for (int k = 0; k < cs->n_networks; ++k) {
+    const gp_network& n = cs->networks[k];
+    if (n.n_nodes < 1 || n.n_lines < 0 || n.n_gens < 0 || n.n_batt < 0)
+      fail(GP_EINVAL, "network %d: bad counts", k);
+    if ((n.n_lines && (!n.line_from || !n.line_to || !n.line_beta)) ||
+        (n.n_gens && (!n.gen_node || !n.gen_cost || !n.gen_emis)) || (n.n_batt && !n.batt_node) ||
+        !n.eta_min || !n.eta_max)
+      fail(GP_EINVAL, "network %d: NULL array", k);
+    for (int l = 0; l < n.n_lines; ++l) {
+      if (n.line_from[l] < 0 || n.line_from[l] >= n.n_nodes || n.line_to[l] < 0 ||
+          n.line_to[l] >= n.n_nodes || n.line_from[l] == n.line_to[l])
+        fail(GP_EINVAL, "network %d line %d: bad endpoints", k, l);
+      if (!(n.line_beta[l] > 0) || !finite(n.line_beta[l]))
+        fail(GP_EINVAL, "network %d line %d: susceptance must be > 0", k, l);
+    }
+    for (int g = 0; g < n.n_gens; ++g) {
+      if (n.gen_node[g] < 0 || n.gen_node[g] >= n.n_nodes)
+        fail(GP_EINVAL, "network %d generator %d: bad node", k, g);
+      if (!(n.gen_cost[g] >= 0) || !finite(n.gen_cost[g]) || !(n.gen_emis[g] >= 0) ||
+          !finite(n.gen_emis[g]))
+        fail(GP_EINVAL, "network %d generator %d: bad cost or emission rate", k, g);
+    }
+    for (int b = 0; b < n.n_batt; ++b)
+      if (n.batt_node[b] < 0 || n.batt_node[b] >= n.n_nodes)
+        fail(GP_EINVAL, "network %d battery %d: bad node", k, b);
+    const int Kn = n.n_gens + n.n_lines + n.n_batt;
+    for (int j = 0; j < Kn; ++j)
+      if (!(n.eta_min[j] >= 0) || !finite(n.eta_min[j]) || !finite(n.eta_max[j]) ||
+          n.eta_max[j] < n.eta_min[j])
+        fail(GP_EINVAL, "network %d capacity %d: bad box [%g, %g]", k, j, n.eta_min[j], n.eta_max[j]);
+  }
+  for (int s = 0; s < cs->n_scenarios; ++s) {
+    const gp_scenario& sc = cs->scenarios[s];
+    if (sc.network < 0 || sc.network >= cs->n_networks) fail(GP_EINVAL, "scenario %d: bad network", s);
+    if (sc.T < 1 || sc.T > 8784) fail(GP_EINVAL, "scenario %d: T must be in [1, 8784]", s);
+    if (!(sc.weight > 0) || !finite(sc.weight)) fail(GP_EINVAL, "scenario %d: weight must be > 0", s);
+    const gp_network& n = cs->networks[sc.network];
+    if ((n.n_gens && !sc.avail) || !sc.load) fail(GP_EINVAL, "scenario %d: NULL profile", s);
+    const int64_t na = (int64_t)n.n_gens * sc.T, nl = (int64_t)n.n_nodes * sc.T;
+    for (int64_t i = 0; i < na; ++i)
+      if (!(sc.avail[i] >= 0.f && sc.avail[i] <= 1.f)) fail(GP_EINVAL, "scenario %d: availability outside [0, 1]", s);
+    for (int64_t i = 0; i < nl; ++i)
+      if (!(sc.load[i] >= 0.f) || !std::isfinite(sc.load[i])) fail(GP_EINVAL, "scenario %d: bad load", s);
+  }
+}
+
+void build(gp_plan* p, const gp_case_desc* cs) {
+  hipStream_t st = p->stream;
+  p->r = cs->r;
+  p->lambda_u = cs->lambda_u;
+  p->eff = cs->eff;
+  p->hours = cs->hours;
+  p->S = cs->n_scenarios;
+  // copy weights of the consensus splitting (see the kernels' header)
+  Weights& w = p->w;
+  w.wb = (float)env_or("GP_WB", 1.0);
+  w.wu = (float)env_or("GP_WU", 1.0);
+  w.wf = (float)env_or("GP_WF", 1.0);
+  w.wth = (float)env_or("GP_WTH", 0.1);
+  w.ws = (float)env_or("GP_WS", 1.0);
+  Tune& tn = p->tune;
+  tn.bsuff = env_or("GP_BSUFF", tn.bsuff);
+  tn.bnec = env_or("GP_BNEC", tn.bnec);
+  tn.art = env_or("GP_ART", tn.art);
+  tn.pw_theta = env_or("GP_PWTHETA", tn.pw_theta);
+  tn.rule = (int)env_or("GP_RULE", tn.rule);
+  tn.flow_rule = (int)env_or("GP_FLOWRULE", tn.flow_rule);
+  tn.clamp = env_or("GP_CLAMP", tn.clamp);
+  w.sig_flow = 1.f / (1.f / w.wf + 2.f / w.wth);
+  w.rho_f = 2.f * w.wb + w.wf;
+  w.rho_b = w.wb + w.ws;
+
+  std::vector<NetDev> nd;
+  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang;
+  std::vector<float> gen_cost, gen_emis, line_beta, sig_bal, rho_th;
+  double qinf = cs->lambda_u;
+  int64_t eta_off = 0;
+  for (int k = 0; k < cs->n_networks; ++k) {
+    const gp_network& n = cs->networks[k];
+    NetDev d{};
+    d.N = n.n_nodes;
+    d.L = n.n_lines;
+    d.G = n.n_gens;
+    d.B = n.n_batt;
+    d.gen_off = (int32_t)gen_node.size();
+    d.line_off = (int32_t)line_from.size();
+    d.node_off = (int32_t)sig_bal.size();
+    d.batt_off = (int32_t)batt_node.size();
+    d.tptr_off = (int32_t)term_ptr.size();
+    d.aptr_off = (int32_t)ang_ptr.size();
+    d.eta_off = (int32_t)eta_off;
+    for (int g = 0; g < d.G; ++g) {
+      gen_node.push_back(n.gen_node[g]);
+      gen_cost.push_back((float)n.gen_cost[g]);
+      gen_emis.push_back((float)n.gen_emis[g]);
+      qinf = std::max(qinf, n.gen_cost[g]);
+    }
+    for (int l = 0; l < d.L; ++l) {
+      line_from.push_back(n.line_from[l]);
+      line_to.push_back(n.line_to[l]);
+      line_beta.push_back((float)n.line_beta[l]);
+    }
+    for (int b = 0; b < d.B; ++b) batt_node.push_back(n.batt_node[b]);
+    // node -> terminals (balance rows) and node -> incident lines (angles)
+    std::vector<std::vector<int32_t>> tl(d.N), al(d.N);
+    std::vector<double> b2(d.N, 0.0);
+    for (int g = 0; g < d.G; ++g) tl[n.gen_node[g]].push_back((g << 2) | TT_GEN);
+    for (int b = 0; b < d.B; ++b) tl[n.batt_node[b]].push_back((b << 2) | TT_BATT);
+    for (int l = 0; l < d.L; ++l) {
+      tl[n.line_to[l]].push_back((l << 2) | TT_LINE_TO);
+      tl[n.line_from[l]].push_back((l << 2) | TT_LINE_FROM);
+      al[n.line_to[l]].push_back(l << 1);
+      al[n.line_from[l]].push_back((l << 1) | 1);
+      const double bb = (double)(float)n.line_beta[l];
+      b2[n.line_to[l]] += bb * bb;
+      b2[n.line_from[l]] += bb * bb;
+    }
+    for (int v = 0; v < d.N; ++v) {
+      term_ptr.push_back((int32_t)term.size());
+      int nterm = 0;
+      for (int32_t c : tl[v]) {
+        term.push_back(c);
+        nterm += ((c & 3) == TT_BATT) ? 2 : 1;  // ch and dis are two copies
+      }
+      sig_bal.push_back((float)(1.0 / (nterm / (double)w.wb + 1.0 / (double)w.wu)));
+      ang_ptr.push_back((int32_t)ang.size());
+      for (int32_t c : al[v]) ang.push_back(c);
+      rho_th.push_back((float)(w.wth * b2[v]));
+    }
+    term_ptr.push_back((int32_t)term.size());
+    ang_ptr.push_back((int32_t)ang.size());
+    nd.push_back(d);
+    NetHost nh;
+    nh.N = d.N;
+    nh.L = d.L;
+    nh.G = d.G;
+    nh.B = d.B;
+    nh.eta_off = eta_off;
+    const int Kn = d.G + d.L + d.B;
+    nh.eta_min.assign(n.eta_min, n.eta_min + Kn);
+    nh.eta_max.assign(n.eta_max, n.eta_max + Kn);
+    p->nets.push_back(nh);
+    eta_off += Kn;
+  }
+  p->K = eta_off;
+  p->qinf = qinf;
+
+  std::vector<ScenDev> sd;
+  std::vector<float> avail, load, taps;
+  std::vector<int> tap_T;  // T -> tap offset cache
+  std::vector<int> tap_off_of;
+  int64_t xoff = 0, yoff = 0;
+  for (int s = 0; s < p->S; ++s) {
+    const gp_scenario& sc = cs->scenarios[s];
+    const NetDev& n = nd[sc.network];
+    ScenDev d{};
+    d.net = sc.network;
+    d.T = sc.T;
+    d.xoff = xoff;
+    d.yoff = yoff;
+    d.aoff = (int64_t)avail.size();
+    d.doff = (int64_t)load.size();
+    const int64_t nx = (int64_t)(n.G + n.L + 2 * n.N + 3 * n.B) * sc.T;
+    const int64_t ny = (int64_t)(n.N + n.L + n.B) * sc.T;
+    avail.insert(avail.end(), sc.avail, sc.avail + (int64_t)n.G * sc.T);
+    load.insert(load.end(), sc.load, sc.load + (int64_t)n.N * sc.T);
+    double einf = 0.0;
+    for (int64_t i = 0; i < (int64_t)n.N * sc.T; ++i) einf = std::max(einf, (double)sc.load[i]);
+    // circulant taps for this horizon (shared across scenarios of equal T)
+    int found = -1;
+    for (size_t q = 0; q < tap_T.size(); ++q)
+      if (tap_T[q] == sc.T) found = tap_off_of[q];
+    if (found < 0) {
+      std::vector<double> h = chain_inverse(sc.T, cs->eff, w.ws);
+      found = (int)taps.size();
+      tap_T.push_back(sc.T);
+      tap_off_of.push_back(found);
+      for (double v : h) taps.push_back((float)v);
+    }
+    d.tap_off = found;
+    {
+      std::vector<double> h = chain_inverse(sc.T, cs->eff, w.ws);
+      int J = sc.T / 2;
+      for (int j = 1; j <= sc.T / 2; ++j) {
+        bool small = true;
+        for (int jj = j; jj <= sc.T / 2; ++jj)
+          if (std::fabs(h[jj]) > 1e-9 * std::fabs(h[0])) small = false;
+        if (small) {
+          J = j - 1;
+          break;
+        }
+      }
+      d.ntap = J + 1;
+    }
+    sd.push_back(d);
+    ScenHost sh;
+    sh.net = sc.network;
+    sh.T = sc.T;
+    sh.weight = sc.weight;
+    sh.einf = einf;
+    sh.xoff = xoff;
+    sh.yoff = yoff;
+    sh.nx = nx;
+    sh.ny = ny;
+    p->scen.push_back(sh);
+    p->max_T = std::max(p->max_T, sc.T);
+    xoff += nx;
+    yoff += ny;
+  }
+  p->nx_tot = xoff;
+  p->ny_tot = yoff;
+
+  p->d_net.upload(nd, st);
+  p->d_scen.upload(sd, st);
+  p->d_gen_node.upload(gen_node, st);
+  p->d_gen_cost.upload(gen_cost, st);
+  p->d_gen_emis.upload(gen_emis, st);
+  p->d_line_from.upload(line_from, st);
+  p->d_line_to.upload(line_to, st);
+  p->d_line_beta.upload(line_beta, st);
+  p->d_batt_node.upload(batt_node, st);
+  p->d_term_ptr.upload(term_ptr, st);
+  p->d_term.upload(term, st);
+  p->d_ang_ptr.upload(ang_ptr, st);
+  p->d_ang.upload(ang, st);
+  p->d_sig_bal.upload(sig_bal, st);
+  p->d_rho_th.upload(rho_th, st);
+  p->d_taps.upload(taps, st);
+  p->d_avail.upload(avail, st);
+  p->d_load.upload(load, st);
+  p->d_eta.alloc((size_t)std::max<int64_t>(p->K, 1));
+  p->d_x.alloc(xoff);
+  p->d_x0.alloc(xoff);
+  p->d_xhat.alloc(xoff);
+  p->d_mask.alloc(xoff);
+  p->d_y.alloc(yoff);
+  p->d_y0.alloc(yoff);
+  p->d_ybar.alloc(yoff);
+  p->d_yhat.alloc(yoff);
+  p->d_cw.alloc(p->S);
+  p->d_cwf.alloc(p->S);
+  p->h_cwf.alloc(p->S);
+  p->d_kbase.alloc(p->S);
+  p->d_active.alloc(p->S);
+  p->d_restart.alloc(p->S);
+  p->h_cw.alloc(p->S);
+  p->h_kbase.alloc(p->S);
+  p->h_active.alloc(p->S);
+  p->h_restart.alloc(p->S);
+  p->has_solution.assign(p->S, 0);
+  p->last_cw.assign(p->S, 0.f);
+  p->last_cwf.assign(p->S, 1.f);
+  for (int q = 0; q < p->S; ++q) p->h_cwf[q] = 1.f;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+Args make_args(gp_plan* p, int adjoint) {
+  Args a{};
+  a.scen = p->d_scen.p;
+  a.net = p->d_net.p;
+  a.vtiles = p->d_vt.p;
+  a.rtiles = p->d_rt.p;
+  a.nvt = p->nvt;
+  a.nrt = p->nrt;
+  a.mode = adjoint;
+  a.gen_node = p->d_gen_node.p;
+  a.gen_cost = p->d_gen_cost.p;
+  a.gen_emis = p->d_gen_emis.p;
+  a.line_from = p->d_line_from.p;
+  a.line_to = p->d_line_to.p;
+  a.line_beta = p->d_line_beta.p;
+  a.batt_node = p->d_batt_node.p;
+  a.term_ptr = p->d_term_ptr.p;
+  a.term = p->d_term.p;
+  a.ang_ptr = p->d_ang_ptr.p;
+  a.ang = p->d_ang.p;
+  a.sig_bal = p->d_sig_bal.p;
+  a.rho_th = p->d_rho_th.p;
+  a.taps = p->d_taps.p;
+  a.avail = p->d_avail.p;
+  a.load = p->d_load.p;
+  a.eta = p->d_eta.p;
+  if (!adjoint) {
+    a.x = p->d_x.p;
+    a.x0 = p->d_x0.p;
+    a.xhat = p->d_xhat.p;
+    a.y = p->d_y.p;
+    a.y0 = p->d_y0.p;
+    a.ybar = p->d_ybar.p;
+    a.yhat = p->d_yhat.p;
+    a.amask = nullptr;
+  } else {
+    a.x = p->a_x.p;
+    a.x0 = p->a_x0.p;
+    a.xhat = p->a_xhat.p;
+    a.y = p->a_y.p;
+    a.y0 = p->a_y0.p;
+    a.ybar = p->a_ybar.p;
+    a.yhat = p->a_yhat.p;
+    a.amask = p->d_mask.p;
+  }
+  a.cw = p->d_cw.p;
+  a.cwf = p->d_cwf.p;
+  a.kbase = p->d_kbase.p;
+  a.active = p->d_active.p;
+  a.restart = p->d_restart.p;
+  a.r = (float)p->r;
+  a.lambda_u = (float)p->lambda_u;
+  a.eff = (float)p->eff;
+  a.hours = (float)p->hours;
+  a.omega = 0.f;
+  a.w = p->w;
+  a.part_v = p->d_part_v.p;
+  a.part_r = p->d_part_r.p;
+  a.ranges = p->d_ranges.p;
+  a.bscen = p->d_bscen.p;
+  a.stats = p->d_stats.p;
+  return a;
+}
+
+void drop_graph(gp_plan* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->graph_mode = -1;
+}
+
+// tiles of the batch: per scenario, variable tiles [gens | lines | nodes |
+// batteries] and row tiles [balance | flow | one per battery chain]
+void build_tiles(gp_plan* p, const std::vector<int>& batch) {
+  if (batch == p->batch && p->nvt > 0) return;
+  const int bs = block_size(p);
+  std::vector<Tile> vt, rt;
+  std::vector<int32_t> ranges;
+  for (int s : batch) {
+    const ScenHost& sh = p->scen[s];
+    const NetHost& n = p->nets[sh.net];
+    const int T = sh.T;
+    const int v0 = (int)vt.size(), r0 = (int)rt.size();
+    auto add = [&](std::vector<Tile>& dst, int cls, int64_t count) {
+      for (int64_t st = 0; st < count; st += bs)
+        dst.push_back(Tile{s, cls, (int32_t)st, (int32_t)std::min<int64_t>(bs, count - st)});
+    };
+    add(vt, VC_GEN, (int64_t)n.G * T);
+    add(vt, VC_LINE, (int64_t)n.L * T);
+    add(vt, VC_NODE, (int64_t)n.N * T);
+    add(vt, VC_BATT, (int64_t)n.B * T);
+    add(rt, RC_BAL, (int64_t)n.N * T);
+    add(rt, RC_FLOW, (int64_t)n.L * T);
+    for (int k = 0; k < n.B; ++k) rt.push_back(Tile{s, RC_SOC, k, 1});
+    ranges.push_back(v0);
+    ranges.push_back((int)vt.size());
+    ranges.push_back(r0);
+    ranges.push_back((int)rt.size());
+  }
+  if ((int64_t)vt.size() > INT32_MAX / 2 || (int64_t)rt.size() > INT32_MAX / 2)
+    fail(GP_EINVAL, "batch too large");
+  hipStream_t st = p->stream;
+  p->d_vt.upload(vt, st);
+  p->d_rt.upload(rt, st);
+  p->nvt = (int)vt.size();
+  p->nrt = (int)rt.size();
+  p->d_ranges.upload(ranges, st);
+  std::vector<int32_t> bs_(batch.begin(), batch.end());
+  p->d_bscen.upload(bs_, st);
+  p->d_part_v.alloc((size_t)std::max(p->nvt, 1) * kStats);
+  p->d_part_r.alloc((size_t)std::max(p->nrt, 1) * kStats);
+  p->d_stats.alloc((size_t)batch.size() * kStats);
+  p->h_stats.alloc((size_t)batch.size() * kStats);
+  p->batch = batch;
+  drop_graph(p);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// Asynchronous copies from pinned memory: the caller must synchronise the
+// stream before it writes the pinned control arrays again.
+void upload_control(gp_plan* p) {
+  hipStream_t st = p->stream;
+  const size_t S = p->S;
+  HIPCHK(hipMemcpyAsync(p->d_cw.p, p->h_cw.p, S * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_cwf.p, p->h_cwf.p, S * sizeof(float), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_kbase.p, p->h_kbase.p, S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_active.p, p->h_active.p, S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_restart.p, p->h_restart.p, S * sizeof(int32_t), hipMemcpyHostToDevice, st));
+}
+
+// one chunk: check_every iterations (the last one writes (xhat, yhat)) and
+// the FP64 statistics of that pair, then the statistics copied to the host
+void enqueue_chunk(gp_plan* p, const Args& a, int ce) {
+  hipStream_t st = p->stream;
+  const int bs = block_size(p);
+  for (int j = 0; j < ce; ++j) {
+    HIPCHK(launch_dual(a, bs, j, j == ce - 1, p->max_T, st));
+    HIPCHK(launch_primal(a, bs, j, j == ce - 1, st));
+  }
+  HIPCHK(launch_check(a, bs, (int)p->batch.size(), st));
+  HIPCHK(hipMemcpyAsync(p->h_stats.p, a.stats, p->batch.size() * kStats * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+}
+
+void run_chunk(gp_plan* p, const Args& a, int ce, int mode) {
+  hipStream_t st = p->stream;
+  if (p->opt.no_graph) {
+    enqueue_chunk(p, a, ce);
+  } else {
+    if (!p->gexec || p->graph_mode != mode) {
+      drop_graph(p);
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_chunk(p, a, ce);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(st, &p->graph));
+      HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+      p->graph_mode = mode;
+    }
+    HIPCHK(hipGraphLaunch(p->gexec, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void run_check_only(gp_plan* p, const Args& a) {
+  hipStream_t st = p->stream;
+  HIPCHK(launch_check(a, block_size(p), (int)p->batch.size(), st));
+  HIPCHK(hipMemcpyAsync(p->h_stats.p, a.stats, p->batch.size() * kStats * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+struct Kkt {
+  double r_pri, r_dual, r_gap, kkt;
+  double r_bal, r_flow, r_soc;  // parts of r_pri by row class
+};
+
+// einf < 0 selects the adjoint scaling: the primal residual is measured
+// relative to the largest entry of the iterate (the adjoint system has a
+// zero right-hand side)
+Kkt kkt_of(const gp_plan* p, const double* st, double einf) {
+  Kkt k;
+  const double den = 1.0 + (einf < 0 ? st[ST_XMAX] : einf);
+  k.r_bal = st[ST_RES_MAX] / den;
+  k.r_flow = st[ST_RESF_MAX] / den;
+  k.r_soc = st[ST_RESS_MAX] / den;
+  k.r_pri = std::max(k.r_bal, std::max(k.r_flow, k.r_soc));
+  k.r_dual = st[ST_DUAL_MAX] / (1.0 + p->qinf);
+  const double P = st[ST_P], D = st[ST_D];
+  k.r_gap = std::fabs(P - D) / (1.0 + std::max(std::fabs(P), std::fabs(D)));
+  k.kkt = std::max(k.r_pri, std::max(k.r_dual, k.r_gap));
+  return k;
+}
+
+// The restarted Halpern loop shared by the dispatch solve (mode 0) and the
+// adjoint solve (mode 1).  Returns the number of unconverged entries.
+int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
+            std::vector<gp_solve_stats>& out, double omega) {
+  const std::vector<int>& batch = p->batch;
+  const int nb = (int)batch.size();
+  Args a = make_args(p, mode);
+  a.omega = (float)omega;
+  const int ce = std::max(2, p->opt.check_every > 0 ? p->opt.check_every : 64);
+  const int max_iter = p->opt.max_iter > 0 ? p->opt.max_iter : 200000;
+  const double tol = p->opt.tol > 0 ? p->opt.tol : 1e-4;
+  const float c0 = (float)(p->opt.rho0 > 0 ? p->opt.rho0 : 10.0);
+  std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+  std::fill(p->h_active.p, p->h_active.p + p->S, 0);
+  std::fill(p->h_kbase.p, p->h_kbase.p + p->S, 0);
+  for (int b = 0; b < nb; ++b) {
+    const int s = batch[b];
+    p->h_restart[s] = 1;
+    p->h_active[s] = 1;
+    const bool w = warm && p->last_cw[s] > 0.f;
+    p->h_cw[s] = w ? p->last_cw[s] : c0;
+    p->h_cwf[s] = w ? p->last_cwf[s] : 1.f;
+  }
+  upload_control(p);
+  // start point: zeros (cold) or the stored (xhat, yhat) (warm)
+  HIPCHK(launch_reset(a, block_size(p), warm ? 0 : 1, p->stream));
+  // the control uploads read pinned host memory asynchronously: wait before
+  // the host rewrites it
+  HIPCHK(hipStreamSynchronize(p->stream));
+  std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+  upload_control(p);
+  run_check_only(p, a);
+  std::vector<double> k_restart(nb), k_last(nb, HUGE_VAL);
+  std::vector<int> inner(nb, 0), total(nb, 0), nrest(nb, 0), done(nb, 0);
+  out.assign(nb, gp_solve_stats{});
+  for (int b = 0; b < nb; ++b) {
+    const Kkt k = kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b]);
+    k_restart[b] = k.kkt;
+    if (k.kkt <= tol) {
+      done[b] = 1;
+      p->h_active[batch[b]] = 0;
+    }
+    out[b].r_pri = k.r_pri;
+    out[b].r_dual = k.r_dual;
+    out[b].r_gap = k.r_gap;
+    out[b].kkt = k.kkt;
+    out[b].cost = p->h_stats[(size_t)b * kStats + ST_P];
+    out[b].emis = p->h_stats[(size_t)b * kStats + ST_EMIS];
+  }
+  int remaining = 0;
+  for (int b = 0; b < nb; ++b) remaining += !done[b];
+  int it = 0;
+  while (remaining > 0 && it < max_iter) {
+    upload_control(p);
+    run_chunk(p, a, ce, mode);
+    it += ce;
+    bool any_restart = false;
+    std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+    for (int b = 0; b < nb; ++b) {
+      if (done[b]) continue;
+      const int s = batch[b];
+      const double* st = p->h_stats.p + (size_t)b * kStats;
+      const Kkt k = kkt_of(p, st, einf[b]);
+      total[b] += ce;
+      inner[b] += ce;
+      out[b].r_pri = k.r_pri;
+      out[b].r_dual = k.r_dual;
+      out[b].r_gap = k.r_gap;
+      out[b].kkt = k.kkt;
+      out[b].cost = st[ST_P];
+      out[b].emis = st[ST_EMIS];
+      out[b].iters = total[b];
+      if (!std::isfinite(k.kkt)) {
+        // numerical breakdown: restart cold with the initial weight
+        p->h_restart[s] = 1;
+        p->h_cw[s] = c0;
+        p->h_cwf[s] = 1.f;
+        any_restart = true;
+        inner[b] = 0;
+        k_restart[b] = HUGE_VAL;
+        k_last[b] = HUGE_VAL;
+        continue;
+      }
+      if (k.kkt <= tol) {
+        done[b] = 1;
+        p->h_active[s] = 0;
+        --remaining;
+        continue;
+      }
+      const Tune& tn = p->tune;
+      const bool go = k.kkt <= tn.bsuff * k_restart[b] ||
+                      (k.kkt <= tn.bnec * k_restart[b] && k.kkt > k_last[b]) ||
+                      inner[b] >= tn.art * total[b];
+      if (p->trace && b == 0)
+        fprintf(stderr, "[trace] mode %d it %d kkt %.3e bal %.2e flow %.2e soc %.2e dual %.2e gap %.2e c %.4g cf %.4g dx %.4g dy %.4g restart %d\n",
+                mode, total[b], k.kkt, k.r_bal, k.r_flow, k.r_soc, k.r_dual, k.r_gap, (double)p->h_cw[s],
+                (double)p->h_cwf[s], std::sqrt(st[ST_DX2]), std::sqrt(st[ST_DY2]), (int)go);
+      k_last[b] = k.kkt;
+      if (go) {
+        const double dx = std::sqrt(st[ST_DX2]), dy = std::sqrt(st[ST_DY2]);
+        const double c = p->h_cw[s];
+        double cn = c;
+        if (tn.rule == 0) {
+          if (dx > 1e-12 && dy > 1e-12 && std::isfinite(dx) && std::isfinite(dy))
+            cn = std::exp(tn.pw_theta * std::log(dy / dx) + (1.0 - tn.pw_theta) * std::log(c));
+        } else {
+          const double f = std::sqrt(std::max(k.r_bal, 1e-16) / std::max(std::max(k.r_dual, k.r_gap), 1e-16));
+          cn = c * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
+        }
+        p->h_cw[s] = (float)std::min(std::max(cn, 1e-6), 1e8);
+        if (tn.flow_rule == 1) {
+          const double f = std::sqrt(std::max(k.r_flow, 1e-16) / std::max(k.r_dual, 1e-16));
+          const double m = p->h_cwf[s] * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
+          p->h_cwf[s] = (float)std::min(std::max(m, 1e-4), 1e4);
+        }
+        p->h_restart[s] = 1;
+        any_restart = true;
+        inner[b] = 0;
+        k_restart[b] = k.kkt;
+        k_last[b] = HUGE_VAL;
+        ++nrest[b];
+      }
+      p->h_kbase[s] = inner[b];
+    }
+    if (any_restart) {
+      upload_control(p);
+      HIPCHK(launch_reset(a, block_size(p), 0, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));  // before the pinned flags are cleared
+      std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+    }
+    if (p->opt.verbose && (it / ce) % 16 == 0) {
+      double worst = 0;
+      for (int b = 0; b < nb; ++b)
+        if (!done[b]) worst = std::max(worst, out[b].kkt);
+      fprintf(stderr, "[gridplan] mode %d iter %d remaining %d worst kkt %.3e\n", mode, it, remaining, worst);
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    out[b].restarts = nrest[b];
+    out[b].status = done[b] ? 0 : 1;
+    out[b].primal_weight = p->h_cw[batch[b]];
+    if (mode == 0) {
+      p->last_cw[batch[b]] = p->h_cw[batch[b]];
+      p->last_cwf[batch[b]] = p->h_cwf[batch[b]];
+    }
+  }
+  return remaining;
+}
+
+void check_batch(gp_plan* p, const int32_t* scen, int32_t nb, std::vector<int>& batch) {
+  if (nb < 1 || !scen) fail(GP_EINVAL, "empty scenario list");
+  if (nb > p->S) fail(GP_EINVAL, "more scenarios listed than the plan holds");
+  std::vector<char> seen(p->S, 0);
+  batch.assign(scen, scen + nb);
+  for (int s : batch) {
+    if (s < 0 || s >= p->S) fail(GP_EINVAL, "scenario index %d out of range [0, %d)", s, p->S);
+    if (seen[s]) fail(GP_EINVAL, "scenario %d listed twice", s);
+    seen[s] = 1;
+  }
+}
+
+void check_eta(const gp_plan* p, const double* eta) {
+  if (!eta) fail(GP_EINVAL, "eta is NULL");
+  for (const NetHost& n : p->nets) {
+    const int Kn = n.G + n.L + n.B;
+    for (int j = 0; j < Kn; ++j) {
+      const double v = eta[n.eta_off + j];
+      const double lo = n.eta_min[j], hi = n.eta_max[j];
+      const double tol = 1e-9 * (1.0 + std::fabs(hi));
+      if (!std::isfinite(v)) fail(GP_EINVAL, "eta[%lld] is not finite", (long long)(n.eta_off + j));
+      if (v < lo - tol || v > hi + tol)
+        fail(GP_EINVAL, "eta[%lld] = %g outside [%g, %g]", (long long)(n.eta_off + j), v, lo, hi);
+    }
+  }
+}
+
+int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, int32_t warm,
+               double* cost_out, gp_solve_stats* stats_out) {
+  std::vector<int> batch;
+  check_batch(p, scen, nb, batch);
+  check_eta(p, eta);
+  if (warm != 0 && warm != 1) fail(GP_EINVAL, "warm_mode must be 0 or 1");
+  std::vector<float> ef(std::max<int64_t>(p->K, 1));
+  for (int64_t j = 0; j < p->K; ++j) ef[j] = (float)eta[j];
+  HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  build_tiles(p, batch);
+  bool all_warm = warm == 1;
+  for (int s : batch) all_warm = all_warm && p->has_solution[s];
+  std::vector<double> einf;
+  for (int s : batch) einf.push_back(p->scen[s].einf);
+  std::vector<gp_solve_stats> st;
+  // a warm start needs a stored solution for every listed scenario; mixed
+  // batches start cold
+  const int rem = iterate(p, 0, einf, all_warm ? 1 : 0, st, 0.0);
+  for (int b = 0; b < nb; ++b) {
+    p->has_solution[batch[b]] = 1;
+    if (cost_out) cost_out[b] = st[b].cost;
+    if (stats_out) stats_out[b] = st[b];
+  }
+  p->solved_batch = batch;
+  p->eta_last.assign(eta, eta + p->K);
+  return rem ? GP_ENOTCONVERGED : GP_OK;
+}
+
+int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,
+              double* h_out) {
+  std::vector<int> batch;
+  check_batch(p, scen, nb, batch);
+  if (!grad_out) fail(GP_EINVAL, "grad_out is NULL");
+  if (!std::isfinite(omega) || omega < 0) fail(GP_EINVAL, "omega must be finite and >= 0");
+  if (batch != p->solved_batch) fail(GP_ESTATE, "dispatch_grad needs a dispatch_solve_batch on the same scenario list first");
+  build_tiles(p, batch);
+  hipStream_t st = p->stream;
+  // objective parts of the forward solution
+  std::fill(p->h_active.p, p->h_active.p + p->S, 0);
+  for (int s : batch) p->h_active[s] = 1;
+  upload_control(p);
+  Args a = make_args(p, 0);
+  run_check_only(p, a);
+  std::vector<double> cost(nb), emis(nb);
+  for (int b = 0; b < nb; ++b) {
+    cost[b] = p->h_stats[(size_t)b * kStats + ST_P];
+    emis[b] = p->h_stats[(size_t)b * kStats + ST_EMIS];
+  }
+  // active-bound mask of the forward solution
+  HIPCHK(launch_mask(a, block_size(p), p->d_mask.p, st));
+  // per-entry output offsets
+  std::vector<int64_t> goff(nb);
+  int64_t ndev = 0;
+  for (int b = 0; b < nb; ++b) {
+    const NetHost& n = p->nets[p->scen[batch[b]].net];
+    goff[b] = ndev;
+    ndev += n.G + n.L + n.B;
+  }
+  p->d_goff.upload(goff, st);
+  p->d_gpart.alloc((size_t)std::max<int64_t>(ndev, 1));
+  p->h_gpart.alloc((size_t)std::max<int64_t>(ndev, 1));
+  Args ag = a;
+  ag.amask = p->d_mask.p;
+  ag.stats = p->d_gpart.p;
+  HIPCHK(launch_grad(ag, p->d_goff.p, nb, ndev, 0, st));
+  HIPCHK(hipMemcpyAsync(p->h_gpart.p, p->d_gpart.p, ndev * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> g(ndev);
+  std::copy(p->h_gpart.p, p->h_gpart.p + ndev, g.begin());
+  int rc = GP_OK;
+  if (omega > 0) {
+    // emissions part: adjoint QP with the active set held fixed
+    if (!p->a_x.p) {
+      p->a_x.alloc(p->nx_tot);
+      p->a_x0.alloc(p->nx_tot);
+      p->a_xhat.alloc(p->nx_tot);
+      p->a_y.alloc(p->ny_tot);
+      p->a_y0.alloc(p->ny_tot);
+      p->a_ybar.alloc(p->ny_tot);
+      p->a_yhat.alloc(p->ny_tot);
+    }
+    drop_graph(p);
+    std::vector<double> einf(nb, -1.0);
+    std::vector<gp_solve_stats> ast;
+    const int rem = iterate(p, 1, einf, 0, ast, omega);
+    drop_graph(p);
+    if (rem) rc = GP_ENOTCONVERGED;
+    Args aa = make_args(p, 1);
+    aa.omega = (float)omega;
+    aa.stats = p->d_gpart.p;
+    HIPCHK(launch_grad(aa, p->d_goff.p, nb, ndev, 1, st));
+    HIPCHK(hipMemcpyAsync(p->h_gpart.p, p->d_gpart.p, ndev * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < ndev; ++i) g[i] += p->h_gpart[i];
+  }
+  // (1/nb) sum_s w_s dh_s/deta, fixed summation order
+  std::fill(grad_out, grad_out + p->K, 0.0);
+  double h = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const ScenHost& sh = p->scen[batch[b]];
+    const NetHost& n = p->nets[sh.net];
+    const int Kn = n.G + n.L + n.B;
+    for (int j = 0; j < Kn; ++j) grad_out[n.eta_off + j] += sh.weight * g[goff[b] + j] / nb;
+    h += sh.weight * (cost[b] + omega * emis[b]) / nb;
+  }
+  if (h_out) *h_out = h;
+  return rc;
+}
+
+int guarded(gp_plan* p, const std::function<int()>& f) {
+  try {
+    const int rc = f();
+    if (p) p->err.clear();
+    return rc;
+  } catch (const GpError& e) {
+    if (p) p->err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    if (p) p->err = e.what();
+    return GP_EHIP;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void* hip_stream) {
+  if (!out) {
+    g_init_error = "out is NULL";
+    return GP_EINVAL;
+  }
+  *out = nullptr;
+  gp_plan* p = nullptr;
+  try {
+    validate_case(cs);
+    if (opt) {
+      if (opt->tol < 0 || opt->max_iter < 0 || opt->check_every < 0 || opt->rho0 < 0)
+        fail(GP_EINVAL, "negative option");
+      if (opt->block != 0 && opt->block != 64 && opt->block != 128 && opt->block != 256 && opt->block != 512)
+        fail(GP_EINVAL, "block must be 0, 64, 128, 256 or 512");
+    }
+    p = new gp_plan();
+    if (opt) p->opt = *opt;
+    if (const char* e = std::getenv("GRIDPLAN_TRACE")) p->trace = std::atoi(e);
+    if (hip_stream) {
+      p->stream = (hipStream_t)hip_stream;
+    } else {
+      // the legacy null stream cannot be captured into a graph: work on a
+      // private non-blocking stream (default priority); every call
+      // synchronises it before returning
+      hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+      if (e != hipSuccess) fail(GP_EHIP, "hipStreamCreateWithFlags failed: %s", hipGetErrorString(e));
+      p->own_stream = true;
+    }
+    build(p, cs);
+  } catch (const GpError& e) {
+    g_init_error = e.msg;
+    delete p;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_init_error = "host allocation failed";
+    delete p;
+    return GP_ENOMEM;
+  }
+  g_init_error.clear();
+  *out = p;
+  return GP_OK;
+}
+
+int dispatch_solve_batch(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb,
+                         int32_t warm_mode, double* cost_out, gp_solve_stats* stats_out) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] { return solve_impl(p, eta, scen, nb, warm_mode, cost_out, stats_out); });
+}
+
+int dispatch_grad(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,
+                  double* h_out) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] { return grad_impl(p, scen, nb, omega, grad_out, h_out); });
+}
+
+int plan_step(gp_plan* p, double alpha, const int32_t* scen, int32_t nb, const double* gamma,
+              double omega, int32_t warm_mode, double* eta_inout, double* phi_out,
+              double* delta_out) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (!(alpha > 0) || !std::isfinite(alpha)) fail(GP_EINVAL, "alpha must be > 0");
+    if (!gamma || !eta_inout) fail(GP_EINVAL, "gamma and eta must not be NULL");
+    for (int64_t j = 0; j < p->K; ++j)
+      if (!std::isfinite(gamma[j])) fail(GP_EINVAL, "gamma[%lld] is not finite", (long long)j);
+    const int rc1 = solve_impl(p, eta_inout, scen, nb, warm_mode, nullptr, nullptr);
+    std::vector<double> g(p->K);
+    double h = 0.0;
+    const int rc2 = grad_impl(p, scen, nb, omega, g.data(), &h);
+    double phi = h;
+    for (int64_t j = 0; j < p->K; ++j) phi += gamma[j] * eta_inout[j];
+    for (const NetHost& n : p->nets) {
+      const int Kn = n.G + n.L + n.B;
+      for (int j = 0; j < Kn; ++j) {
+        const int64_t q = n.eta_off + j;
+        const double d = gamma[q] + g[q];
+        if (delta_out) delta_out[q] = d;
+        eta_inout[q] = std::min(std::max(eta_inout[q] - alpha * d, n.eta_min[j]), n.eta_max[j]);
+      }
+    }
+    if (phi_out) *phi_out = phi;
+    return (rc1 == GP_OK && rc2 == GP_OK) ? GP_OK : GP_ENOTCONVERGED;
+  });
+}
+
+int dispatch_get_solution(gp_plan* p, int32_t s, float* x_out, double* y_out, int64_t* n_x,
+                          int64_t* n_y) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (s < 0 || s >= p->S) fail(GP_EINVAL, "scenario index out of range");
+    const ScenHost& sh = p->scen[s];
+    if (n_x) *n_x = sh.nx;
+    if (n_y) *n_y = sh.ny;
+    if ((x_out || y_out) && !p->has_solution[s]) fail(GP_ESTATE, "scenario %d has no solution yet", s);
+    if (x_out)
+      HIPCHK(hipMemcpyAsync(x_out, p->d_xhat.p + sh.xoff, sh.nx * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+    if (y_out)
+      HIPCHK(hipMemcpyAsync(y_out, p->d_yhat.p + sh.yoff, sh.ny * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return GP_OK;
+  });
+}
+
+int dispatch_set_start(gp_plan* p, int32_t s, const float* x, const double* y) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (s < 0 || s >= p->S) fail(GP_EINVAL, "scenario index out of range");
+    if (!x) fail(GP_EINVAL, "x is NULL");
+    const ScenHost& sh = p->scen[s];
+    for (int64_t i = 0; i < sh.nx; ++i)
+      if (!std::isfinite(x[i])) fail(GP_EINVAL, "x[%lld] is not finite", (long long)i);
+    if (y)
+      for (int64_t i = 0; i < sh.ny; ++i)
+        if (!std::isfinite(y[i])) fail(GP_EINVAL, "y[%lld] is not finite", (long long)i);
+    HIPCHK(hipMemcpyAsync(p->d_xhat.p + sh.xoff, x, sh.nx * sizeof(float), hipMemcpyHostToDevice, p->stream));
+    if (y)
+      HIPCHK(hipMemcpyAsync(p->d_yhat.p + sh.yoff, y, sh.ny * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    else if (!p->has_solution[s])
+      HIPCHK(hipMemsetAsync(p->d_yhat.p + sh.yoff, 0, sh.ny * sizeof(double), p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->has_solution[s] = 1;
+    return GP_OK;
+  });
+}
+
+int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters, double* ms_dual,
+                     double* ms_primal) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    std::vector<int> batch;
+    check_batch(p, scen, nb, batch);
+    if (iters < 1) fail(GP_EINVAL, "iters must be >= 1");
+    if (!ms_dual || !ms_primal) fail(GP_EINVAL, "outputs must not be NULL");
+    if (batch != p->solved_batch) fail(GP_ESTATE, "plan_time_sweeps needs a solve of the same scenario list first");
+    build_tiles(p, batch);
+    hipStream_t st = p->stream;
+    std::fill(p->h_active.p, p->h_active.p + p->S, 0);
+    std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+    for (int s : batch) {
+      p->h_active[s] = 1;
+      p->h_kbase[s] = 0;
+      p->h_cw[s] = p->last_cw[s] > 0.f ? p->last_cw[s] : 10.f;
+      p->h_cwf[s] = p->last_cwf[s];
+    }
+    upload_control(p);
+    HIPCHK(hipStreamSynchronize(st));
+    Args a = make_args(p, 0);
+    std::vector<hipEvent_t> ev(4 * iters);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    const int bs = block_size(p);
+    for (int j = 0; j < iters; ++j) {
+      HIPCHK(hipEventRecord(ev[4 * j], st));
+      HIPCHK(launch_dual(a, bs, j, 0, p->max_T, st));
+      HIPCHK(hipEventRecord(ev[4 * j + 1], st));
+      HIPCHK(hipEventRecord(ev[4 * j + 2], st));
+      HIPCHK(launch_primal(a, bs, j, 0, st));
+      HIPCHK(hipEventRecord(ev[4 * j + 3], st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    double sd = 0, sp = 0;
+    for (int j = 0; j < iters; ++j) {
+      float a1 = 0, a2 = 0;
+      HIPCHK(hipEventElapsedTime(&a1, ev[4 * j], ev[4 * j + 1]));
+      HIPCHK(hipEventElapsedTime(&a2, ev[4 * j + 2], ev[4 * j + 3]));
+      sd += a1;
+      sp += a2;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    *ms_dual = sd / iters;
+    *ms_primal = sp / iters;
+    return GP_OK;
+  });
+}
+
+int plan_sizes(const gp_plan* p, int64_t* K, int32_t* S) {
+  if (!p) return GP_EINVAL;
+  if (K) *K = p->K;
+  if (S) *S = p->S;
+  return GP_OK;
+}
+
+void plan_free(gp_plan* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  delete p;
+}
+
+const char* plan_last_error(const gp_plan* p) {
+  if (!p) return g_init_error.c_str();
+  return p->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+"""ctypes binding of libgridplan (argument marshalling only).
+
+Every step of the dispatch solve, the capacity gradient and the planning
+step runs in the HIP library; this module only converts a
+``cases.Case`` into the C descriptors of ``include/gridplan.h`` and numpy
+arrays into pointers.  It fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgridplan.so")
+
+GP_OK, GP_ENOTCONVERGED = 0, 1
+GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ESTATE = -1, -2, -3, -4
+
+EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "plan_step",
+           "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_sizes",
+           "plan_free", "plan_last_error")
+
+
+class GridplanError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gridplan error {code}: {msg}")
+        self.code = code
+
+
+class NotBuiltError(RuntimeError):
+    pass
+
+
+class gp_network(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_lines", C.c_int32), ("n_gens", C.c_int32),
+                ("n_batt", C.c_int32),
+                ("line_from", C.POINTER(C.c_int32)), ("line_to", C.POINTER(C.c_int32)),
+                ("line_beta", C.POINTER(C.c_double)), ("gen_node", C.POINTER(C.c_int32)),
+                ("gen_cost", C.POINTER(C.c_double)), ("gen_emis", C.POINTER(C.c_double)),
+                ("batt_node", C.POINTER(C.c_int32)), ("eta_min", C.POINTER(C.c_double)),
+                ("eta_max", C.POINTER(C.c_double))]
+
+
+class gp_scenario(C.Structure):
+    _fields_ = [("network", C.c_int32), ("T", C.c_int32), ("avail", C.POINTER(C.c_float)),
+                ("load", C.POINTER(C.c_float)), ("weight", C.c_double)]
+
+
+class gp_case_desc(C.Structure):
+    _fields_ = [("n_networks", C.c_int32), ("networks", C.POINTER(gp_network)),
+                ("n_scenarios", C.c_int32), ("scenarios", C.POINTER(gp_scenario)),
+                ("r", C.c_double), ("lambda_u", C.c_double), ("eff", C.c_double),
+                ("hours", C.c_double)]
+
+
+class gp_options(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
+                ("block", C.c_int32), ("no_graph", C.c_int32), ("rho0", C.c_double),
+                ("verbose", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class gp_solve_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
+                ("pad", C.c_int32), ("r_pri", C.c_double), ("r_dual", C.c_double),
+                ("r_gap", C.c_double), ("kkt", C.c_double), ("cost", C.c_double),
+                ("emis", C.c_double), ("primal_weight", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgridplan.so (raises NotBuiltError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise NotBuiltError(f"{path} not found: run `python -m paper_2410_13055_amd.build`")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    lib.plan_init.argtypes = [P(C.c_void_p), P(gp_case_desc), P(gp_options), C.c_void_p]
+    lib.plan_init.restype = C.c_int
+    lib.dispatch_solve_batch.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32,
+                                         C.c_int32, P(C.c_double), P(gp_solve_stats)]
+    lib.dispatch_solve_batch.restype = C.c_int
+    lib.dispatch_grad.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_double,
+                                  P(C.c_double), P(C.c_double)]
+    lib.dispatch_grad.restype = C.c_int
+    lib.plan_step.argtypes = [C.c_void_p, C.c_double, P(C.c_int32), C.c_int32, P(C.c_double),
+                              C.c_double, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]
+    lib.plan_step.restype = C.c_int
+    lib.dispatch_get_solution.argtypes = [C.c_void_p, C.c_int32, P(C.c_float), P(C.c_double),
+                                          P(C.c_int64), P(C.c_int64)]
+    lib.dispatch_get_solution.restype = C.c_int
+    lib.dispatch_set_start.argtypes = [C.c_void_p, C.c_int32, P(C.c_float), P(C.c_double)]
+    lib.dispatch_set_start.restype = C.c_int
+    lib.plan_time_sweeps.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_int32,
+                                     P(C.c_double), P(C.c_double)]
+    lib.plan_time_sweeps.restype = C.c_int
+    lib.plan_sizes.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32)]
+    lib.plan_sizes.restype = C.c_int
+    lib.plan_free.argtypes = [C.c_void_p]
+    lib.plan_free.restype = None
+    lib.plan_last_error.argtypes = [C.c_void_p]
+    lib.plan_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray], ct):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class _Descriptor:
+    """Owns the numpy arrays the C descriptor points into."""
+
+    def __init__(self, case):
+        self.keep = []
+        nets = (gp_network * len(case.networks))()
+        for i, n in enumerate(case.networks):
+            arrs = dict(
+                line_from=np.ascontiguousarray(n.line_from, np.int32),
+                line_to=np.ascontiguousarray(n.line_to, np.int32),
+                line_beta=np.ascontiguousarray(n.line_beta, np.float64),
+                gen_node=np.ascontiguousarray(n.gen_node, np.int32),
+                gen_cost=np.ascontiguousarray(n.gen_cost, np.float64),
+                gen_emis=np.ascontiguousarray(n.gen_emis, np.float64),
+                batt_node=np.ascontiguousarray(n.batt_node, np.int32),
+                eta_min=np.ascontiguousarray(n.eta_min, np.float64),
+                eta_max=np.ascontiguousarray(n.eta_max, np.float64))
+            self.keep.append(arrs)
+            nets[i] = gp_network(
+                n.n_nodes, n.n_lines, n.n_gens, n.n_batt,
+                _ptr(arrs["line_from"], C.c_int32), _ptr(arrs["line_to"], C.c_int32),
+                _ptr(arrs["line_beta"], C.c_double), _ptr(arrs["gen_node"], C.c_int32),
+                _ptr(arrs["gen_cost"], C.c_double), _ptr(arrs["gen_emis"], C.c_double),
+                _ptr(arrs["batt_node"], C.c_int32), _ptr(arrs["eta_min"], C.c_double),
+                _ptr(arrs["eta_max"], C.c_double))
+        scs = (gp_scenario * len(case.scenarios))()
+        for i, s in enumerate(case.scenarios):
+            av = np.ascontiguousarray(s.avail, np.float32)
+            ld = np.ascontiguousarray(s.load, np.float32)
+            self.keep.append((av, ld))
+            scs[i] = gp_scenario(int(s.network), int(s.T), _ptr(av, C.c_float), _ptr(ld, C.c_float),
+                                 float(s.weight))
+        self.nets, self.scs = nets, scs
+        self.desc = gp_case_desc(len(case.networks), nets, len(case.scenarios), scs,
+                                 float(case.r), float(case.lambda_u), float(case.eff), float(case.hours))
+
+
+def options(tol=1e-4, max_iter=0, check_every=0, block=0, no_graph=0, rho0=0.0, verbose=0):
+    return gp_options(float(tol), int(max_iter), int(check_every), int(block), int(no_graph),
+                      float(rho0), int(verbose))
+
+
+def current_stream():
+    """The HIP stream torch is using on the current device (None when torch
+    has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            h = torch.cuda.current_stream().cuda_stream
+            # the null stream cannot be captured; the library then uses its own
+            return C.c_void_p(h) if h else None
+    except Exception:
+        pass
+    return None
+
+
+class Plan:
+    """A plan on the GPU: the case's device layout plus solver state."""
+
+    def __init__(self, case, opts: Optional[gp_options] = None, stream=None):
+        self.lib = load()
+        self.case = case
+        self._desc = _Descriptor(case)
+        self.opts = opts if opts is not None else options()
+        h = C.c_void_p()
+        rc = self.lib.plan_init(C.byref(h), C.byref(self._desc.desc), C.byref(self.opts),
+                                stream if stream is not None else None)
+        if rc != GP_OK:
+            raise GridplanError(rc, self.lib.plan_last_error(None).decode())
+        self.h = h
+        K = C.c_int64()
+        S = C.c_int32()
+        self.lib.plan_sizes(self.h, C.byref(K), C.byref(S))
+        self.K, self.S = int(K.value), int(S.value)
+
+    def _check(self, rc, allow_nc=True):
+        if rc == GP_OK or (allow_nc and rc == GP_ENOTCONVERGED):
+            return rc
+        raise GridplanError(rc, self.lib.plan_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @staticmethod
+    def _idx(scen: Sequence[int]):
+        return np.ascontiguousarray(np.asarray(scen, dtype=np.int32))
+
+    def solve(self, eta, scen, warm: int = 0):
+        """dispatch_solve_batch: returns (cost[nb], [stats dict], rc)."""
+        eta = np.ascontiguousarray(eta, np.float64)
+        idx = self._idx(scen)
+        nb = idx.shape[0]
+        cost = np.zeros(nb)
+        st = (gp_solve_stats * max(nb, 1))()
+        rc = self.lib.dispatch_solve_batch(self.h, _ptr(eta, C.c_double), _ptr(idx, C.c_int32), nb,
+                                           int(warm), _ptr(cost, C.c_double), st)
+        self._check(rc)
+        return cost, [st[i].as_dict() for i in range(nb)], rc
+
+    def grad(self, scen, omega: float = 0.0):
+        """dispatch_grad: returns (grad[K], weighted mean h, rc)."""
+        idx = self._idx(scen)
+        g = np.zeros(max(self.K, 1))
+        h = C.c_double()
+        rc = self.lib.dispatch_grad(self.h, _ptr(idx, C.c_int32), idx.shape[0], float(omega),
+                                    _ptr(g, C.c_double), C.byref(h))
+        self._check(rc)
+        return g[:self.K], float(h.value), rc
+
+    def step(self, alpha, scen, gamma, eta, omega: float = 0.0, warm: int = 1):
+        """plan_step: returns (new eta, phi at the input eta, Delta, rc)."""
+        idx = self._idx(scen)
+        gam = np.ascontiguousarray(gamma, np.float64)
+        e = np.array(eta, dtype=np.float64, copy=True)
+        phi = C.c_double()
+        delta = np.zeros(max(self.K, 1))
+        rc = self.lib.plan_step(self.h, float(alpha), _ptr(idx, C.c_int32), idx.shape[0],
+                                _ptr(gam, C.c_double), float(omega), int(warm), _ptr(e, C.c_double),
+                                C.byref(phi), _ptr(delta, C.c_double))
+        self._check(rc)
+        return e, float(phi.value), delta[:self.K], rc
+
+    def solution(self, s: int):
+        """(x FP32, y FP64) of scenario s in the canonical orders."""
+        nx, ny = C.c_int64(), C.c_int64()
+        self._check(self.lib.dispatch_get_solution(self.h, int(s), None, None, C.byref(nx), C.byref(ny)),
+                    allow_nc=False)
+        x = np.zeros(nx.value, np.float32)
+        y = np.zeros(ny.value, np.float64)
+        self._check(self.lib.dispatch_get_solution(self.h, int(s), _ptr(x, C.c_float), _ptr(y, C.c_double),
+                                                   None, None), allow_nc=False)
+        return x, y
+
+    def time_sweeps(self, scen, iters: int = 50):
+        """plan_time_sweeps: mean (ms_dual, ms_primal) per launch."""
+        idx = self._idx(scen)
+        md, mp = C.c_double(), C.c_double()
+        self._check(self.lib.plan_time_sweeps(self.h, _ptr(idx, C.c_int32), idx.shape[0], int(iters),
+                                              C.byref(md), C.byref(mp)), allow_nc=False)
+        return md.value, mp.value
+
+    def set_start(self, s: int, x, y=None):
+        x = np.ascontiguousarray(x, np.float32)
+        y = None if y is None else np.ascontiguousarray(y, np.float64)
+        self._check(self.lib.dispatch_set_start(self.h, int(s), _ptr(x, C.c_float), _ptr(y, C.c_double)),
+                    allow_nc=False)
