@@ -51,6 +51,18 @@ def algorithmic_bytes(case, scen):
     return dict(primal=12 * nx + 8 * ny + 4 * gt, dual=4 * nx + 32 * ny + 4 * nt, n_x=nx, n_y=ny)
 
 
+def _read_traffic_table():
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    tab = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            for line in fh:
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                if len(cells) >= 3 and cells[0].startswith("k_") and "@config" in cells[0]:
+                    tab[cells[0]] = {"bytes_per_launch": float(cells[1]), "source_hash": cells[2]}
+    return tab
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("gp_kernels.hip", "gp_device.h"):
@@ -62,12 +74,7 @@ def kernel_source_hash():
 def measured_traffic(kernel, workload_id):
     """HBM bytes per launch from committed rocprofv3 counter runs, used only
     while the kernel source is unchanged since they were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        tab = json.load(fh)
-    ent = tab.get(f"{kernel}@config{workload_id}")
+    ent = _read_traffic_table().get(f"{kernel}@config{workload_id}")
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -103,6 +110,55 @@ def cpu_baseline(case, hours=24):
                       f"{dt:.1f} s"}
 
 
+def summarize(stats_csv, fetch_csv, write_csv, pmc_line, workload_id, commands):
+    """Turn rocprofv3 outputs into the short text summaries kept in profiles/:
+    per-kernel durations, and HBM bytes per launch of the timed sweep kernels
+    from FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by what the same
+    counters read for a 1 GiB fill (writes) and a 1 GiB sum (reads)."""
+    import csv
+    from collections import defaultdict
+
+    info = json.loads(pmc_line)
+    out = [f"# rocprofv3 summary: {info['pmc_run']}", "", "Commands:", ""]
+    out += [f"    {c}" for c in commands] + [""]
+    out += ["## Kernel durations (--kernel-trace --stats)", "",
+            "| kernel | calls | average us | total ms | share |", "|---|---|---|---|---|"]
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            out.append(f"| `{r['Name'][:70]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f}% |")
+    per = defaultdict(lambda: defaultdict(list))
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                per[r["Kernel_Name"]][name].append(float(r["Counter_Value"]))
+
+    def avg(kern_prefix, counter):
+        vals = [v for k, d in per.items() if k.startswith(kern_prefix) for v in d[counter]]
+        return sum(vals) / len(vals) if vals else float("nan")
+    gib = 1 << 30
+    fill_w = avg("void at::native::vectorized_elementwise_kernel", "WRITE_SIZE") * 1024
+    sum_r = avg("void at::native::reduce_kernel", "FETCH_SIZE") * 1024
+    fw, fr = gib / fill_w, gib / sum_r
+    out += ["", "## HBM traffic per launch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
+            f"Calibration: a 1 GiB fill reads WRITE_SIZE = {fill_w / gib:.4f} GiB (write factor "
+            f"{fw:.4f}); a 1 GiB sum reads FETCH_SIZE = {sum_r / gib:.4f} GiB (read factor {fr:.4f}).", "",
+            "| kernel | FETCH KiB | WRITE KiB | traffic bytes (scaled) | algorithmic bytes |",
+            "|---|---|---|---|---|"]
+    rows = []
+    for kern, alg in (("k_primal", info["primal"]), ("k_dual", info["dual"])):
+        pre = f"void gp::{kern}<256, 1>"
+        f_, w_ = avg(pre, "FETCH_SIZE"), avg(pre, "WRITE_SIZE")
+        traffic = f_ * 1024 * fr + w_ * 1024 * fw
+        out.append(f"| `{kern}<256, 1>` | {f_:.0f} | {w_:.0f} | {traffic:.0f} | {alg} |")
+        rows.append((kern, traffic))
+    out += ["", "Table read by bench.py (valid while the kernel source hash matches):", "",
+            "| key | bytes_per_launch | source_hash |", "|---|---|---|"]
+    h = kernel_source_hash()
+    out += [f"| {k}@config{workload_id} | {t:.0f} | {h} |" for k, t in rows]
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +168,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-hours", type=int, default=24)
     ap.add_argument("--sweep-iters", type=int, default=50)
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for hardware counters: one iteration chunk, 10 timed sweeps of "
+                         "each kernel and a 1 GiB device copy that calibrates the byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
@@ -132,6 +191,23 @@ def main():
     eta = case.eta_min()
     omega = case.omega
     print(f"[bench] {WORKLOADS[args.config]}", file=sys.stderr, flush=True)
+    if args.pmc_run:
+        plan = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
+        plan.solve(eta, scen, warm=0)
+        md, mp = plan.time_sweeps(scen, 10)
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)  # 1 GiB read + 1 GiB written
+        total = a.sum()  # reduction kernel: 1 GiB read (calibrates the read counter)
+        torch.cuda.synchronize()
+        assert float(total) == float(1 << 28)
+        ab = algorithmic_bytes(case, scen)
+        print(json.dumps({"pmc_run": WORKLOADS[args.config], "ms_dual": md, "ms_primal": mp,
+                          "copy_bytes": 1 << 30, **ab}), flush=True)
+        plan.close()
+        return
     plan = gridplan.Plan(case, gridplan.options(), stream=gridplan.current_stream())
     for w in range(args.warmup):
         _, st, _ = plan.solve(eta, scen, warm=0)

@@ -441,7 +441,7 @@ def adjoint_lsq(qp: QP, free: np.ndarray, g: np.ndarray):
     return msolve(EF @ g[free]), rankdef
 
 
-def polish(qp: QP, sol: Solution, tol_act: float = 1e-9, max_rounds: int = 30) -> Solution:
+def polish(qp: QP, sol: Solution, tol_act: float = 1e-9, max_rounds: int = 60) -> Solution:
     """Exact active-set polish.
 
     Bounds are first classified from the interior-point complementarity pairs
@@ -465,6 +465,7 @@ def polish(qp: QP, sol: Solution, tol_act: float = 1e-9, max_rounds: int = 30) -
     su = np.where(np.isfinite(hi), hi - x, INF)
     at_lo = (np.isfinite(lo) & (zl_f > sl) & ~fixed) | fixed
     at_hi = np.isfinite(hi) & (zu_f > su) & ~at_lo
+    ipm_lo, ipm_hi = at_lo.copy(), at_hi.copy()
     bscale = 1.0 + np.abs(qp.q).max()
     xs = 1.0 + max(np.abs(lo[np.isfinite(lo)]).max(initial=0), np.abs(hi[np.isfinite(hi)]).max(initial=0))
     ok = False
@@ -479,8 +480,23 @@ def polish(qp: QP, sol: Solution, tol_act: float = 1e-9, max_rounds: int = 30) -
         wrong_hi = at_hi & ~fixed & (z < -1e-9 * bscale)
         wrong_lo = at_lo & ~fixed & (z > 1e-9 * bscale)
         if not (below.any() or above.any() or wrong_hi.any() or wrong_lo.any()):
-            ok = np.abs(qp.E @ xp - qp.e).max(initial=0) <= 1e-8 * (1 + np.abs(qp.e).max(initial=0))
-            break
+            resid = np.abs(qp.E @ xp - qp.e)
+            bad = resid > 1e-8 * (1 + np.abs(qp.e).max(initial=0))
+            if not bad.any():
+                ok = True
+                break
+            # rows the active set makes unsatisfiable (a weakly active entry
+            # was classified active): release the active entry of those rows
+            # with the smallest multiplier
+            touch = np.asarray(np.abs(qp.E[bad]).sum(axis=0)).ravel() > 0
+            cand = np.where(touch & (at_lo | at_hi) & ~fixed)[0]
+            if cand.size == 0:
+                break
+            j = cand[np.argmin(np.abs(z[cand]))]
+            at_lo[j] = False
+            at_hi[j] = False
+            y0 = yp
+            continue
         at_lo = (at_lo & ~wrong_lo) | below
         at_hi = (at_hi & ~wrong_hi) | above
         y0 = yp
@@ -491,9 +507,16 @@ def polish(qp: QP, sol: Solution, tol_act: float = 1e-9, max_rounds: int = 30) -
         out.x, out.y, out.z = np.clip(xp, lo, hi), yp, z
         out.obj = primal_objective(qp, out.x)
         out.polished = True
+        out.active_lo = at_lo
+        out.active_hi = at_hi
+    else:
+        # the refinement did not settle: a weakly active entry (slack and
+        # multiplier both near zero) sits at a kink of the dispatch map; keep
+        # the interior-point solution and its classification
+        out.active_lo = ipm_lo
+        out.active_hi = ipm_hi
+        weak = True
     out.degenerate = bool(weak or rankdef)
-    out.active_lo = at_lo
-    out.active_hi = at_hi
     return out
 
 

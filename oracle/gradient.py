@@ -48,8 +48,8 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
 
     Returns the gradient, the envelope value (cost part only), the adjoint w
     and a flag for points where the map is not differentiable (weakly active
-    bounds, or a non-unique adjoint that reaches capacity-dependent bounds)."""
-    assert sol.polished, "gradient needs a polished (exact active set) solution"
+    bounds, or a solution whose active set the polish could not settle; there
+    the value is one element of the generalised gradient)."""
     at_lo, at_hi = sol.active_lo, sol.active_hi
     free = ~(at_lo | at_hi)
     g = loss_gradient_x(qp, sol.x, omega)
@@ -63,7 +63,7 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
            (at_lo & (qp.lo_idx >= 0) & (qp.lo_coef != 0)))
     fixed = np.isfinite(qp.lo) & np.isfinite(qp.hi) & (qp.hi - qp.lo <= 1e-12 * (1 + np.abs(qp.hi)))
     weak = dep & ~fixed & (np.abs(sol.z) < 1e-7 * bscale)
-    return dict(grad=grad, envelope=env, w=w, dl_dx=dl_dx, kink=bool(weak.any()),
+    return dict(grad=grad, envelope=env, w=w, dl_dx=dl_dx, kink=bool(weak.any() or not sol.polished),
                 rank_deficient=rankdef)
 
 

@@ -6,7 +6,7 @@
 
 namespace gp {
 
-constexpr int kStats = 12;  // FP64 statistics per tile / per scenario
+constexpr int kStats = 14;  // FP64 statistics per tile / per scenario
 
 // statistic slots (sums unless noted)
 enum Stat {
@@ -21,6 +21,8 @@ enum Stat {
   ST_DY2 = 8,       // sum rowden (yhat - y0)^2
   ST_EMIS = 9,      // sum emis_g p
   ST_FUEL = 10,     // sum cost_g p
+  ST_RES2 = 11,     // sum (E x - e)^2 over all rows
+  ST_DUAL2 = 12,    // sum (E'y - q - r x)^2 over free entries
 };
 constexpr int kMaxStats = 5;  // slots [0, kMaxStats) are maxima, the rest sums
 

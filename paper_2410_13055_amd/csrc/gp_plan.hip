@@ -18,8 +18,8 @@
 #include "gp_device.h"
 
 namespace gp {
-hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st);
-hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st);
+hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st, int timed = 0);
+hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed = 0);
 hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st);
 hipError_t launch_reset(const Args& a, int bs, int cold, hipStream_t st);
 hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st);
@@ -116,6 +116,8 @@ struct ScenHost {
   int net, T;
   double weight;
   double einf;  // ||load||_inf
+  double e2;    // ||load||_2
+  double q2;    // ||q||_2
   int64_t xoff, yoff, nx, ny;
 };
 
@@ -127,10 +129,14 @@ struct ScenHost {
 struct Tune {
   double bsuff = 0.2;     // restart when the KKT residual fell by this factor
   double bnec = 0.8;      // ... or by this factor and stopped improving
-  double art = 0.36;      // ... or the cycle is this fraction of all iterations
+  double art = 0.2;       // ... or the cycle is this fraction of all iterations
   double pw_theta = 0.5;  // smoothing of the primal-weight update
-  int rule = 0;           // 0: balance weighted primal/dual movement; 1: balance residuals
-  int flow_rule = 0;      // 1: adapt the flow-class multiplier at restarts
+  int rule = 1;           // 0: balance weighted primal/dual movement; 1: balance residuals
+  double gain = 0.25;     // exponent of the residual-balancing update
+  int arule = 0;          // rule of the adjoint solve (-1: same as rule)
+  int flow_rule = 1;      // 1: adapt the flow-class multiplier at restarts
+  int rmetric = 1;        // restart decisions on 0: the max-norm KKT, 1: the 2-norm KKT
+  int stop_norm = 0;      // stopping test on 0: the max-norm KKT, 2: the 2-norm KKT
   double clamp = 10.0;    // largest factor of one weight update
 };
 
@@ -299,6 +305,10 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   tn.rule = (int)env_or("GP_RULE", tn.rule);
   tn.flow_rule = (int)env_or("GP_FLOWRULE", tn.flow_rule);
   tn.clamp = env_or("GP_CLAMP", tn.clamp);
+  tn.rmetric = (int)env_or("GP_RMETRIC", tn.rmetric);
+  tn.gain = env_or("GP_GAIN", tn.gain);
+  tn.arule = (int)env_or("GP_ARULE", tn.arule);
+  tn.stop_norm = (int)env_or("GP_NORM", tn.stop_norm);
   w.sig_flow = 1.f / (1.f / w.wf + 2.f / w.wth);
   w.rho_f = 2.f * w.wb + w.wf;
   w.rho_b = w.wb + w.ws;
@@ -397,8 +407,16 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     const int64_t ny = (int64_t)(n.N + n.L + n.B) * sc.T;
     avail.insert(avail.end(), sc.avail, sc.avail + (int64_t)n.G * sc.T);
     load.insert(load.end(), sc.load, sc.load + (int64_t)n.N * sc.T);
-    double einf = 0.0;
-    for (int64_t i = 0; i < (int64_t)n.N * sc.T; ++i) einf = std::max(einf, (double)sc.load[i]);
+    double einf = 0.0, e2 = 0.0, q2 = 0.0;
+    for (int64_t i = 0; i < (int64_t)n.N * sc.T; ++i) {
+      einf = std::max(einf, (double)sc.load[i]);
+      e2 += (double)sc.load[i] * sc.load[i];
+    }
+    {
+      const gp_network& nn = cs->networks[sc.network];
+      for (int g = 0; g < nn.n_gens; ++g) q2 += nn.gen_cost[g] * nn.gen_cost[g] * sc.T;
+      q2 += cs->lambda_u * cs->lambda_u * (double)nn.n_nodes * sc.T;
+    }
     // circulant taps for this horizon (shared across scenarios of equal T)
     int found = -1;
     for (size_t q = 0; q < tap_T.size(); ++q)
@@ -431,6 +449,8 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     sh.T = sc.T;
     sh.weight = sc.weight;
     sh.einf = einf;
+    sh.e2 = std::sqrt(e2);
+    sh.q2 = std::sqrt(q2);
     sh.xoff = xoff;
     sh.yoff = yoff;
     sh.nx = nx;
@@ -668,12 +688,13 @@ void run_check_only(gp_plan* p, const Args& a) {
 struct Kkt {
   double r_pri, r_dual, r_gap, kkt;
   double r_bal, r_flow, r_soc;  // parts of r_pri by row class
+  double kkt2;                  // the same test with relative 2-norms
 };
 
 // einf < 0 selects the adjoint scaling: the primal residual is measured
 // relative to the largest entry of the iterate (the adjoint system has a
 // zero right-hand side)
-Kkt kkt_of(const gp_plan* p, const double* st, double einf) {
+Kkt kkt_of(const gp_plan* p, const double* st, double einf, double e2 = 0.0, double q2 = 1.0) {
   Kkt k;
   const double den = 1.0 + (einf < 0 ? st[ST_XMAX] : einf);
   k.r_bal = st[ST_RES_MAX] / den;
@@ -684,6 +705,9 @@ Kkt kkt_of(const gp_plan* p, const double* st, double einf) {
   const double P = st[ST_P], D = st[ST_D];
   k.r_gap = std::fabs(P - D) / (1.0 + std::max(std::fabs(P), std::fabs(D)));
   k.kkt = std::max(k.r_pri, std::max(k.r_dual, k.r_gap));
+  const double rp2 = std::sqrt(st[ST_RES2]) / (1.0 + (einf < 0 ? st[ST_XMAX] : e2));
+  const double rd2 = std::sqrt(st[ST_DUAL2]) / (1.0 + q2);
+  k.kkt2 = std::max(rp2, std::max(rd2, k.r_gap));
   return k;
 }
 
@@ -719,13 +743,23 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
   upload_control(p);
   run_check_only(p, a);
+  std::vector<double> e2(nb, 0.0), q2(nb, 1.0);
+  for (int b = 0; b < nb; ++b) {
+    if (mode == 0) {
+      e2[b] = p->scen[batch[b]].e2;
+      q2[b] = p->scen[batch[b]].q2;
+    }
+  }
+  const Tune& tn = p->tune;
+  auto stop_of = [&](const Kkt& k) { return tn.stop_norm == 2 ? k.kkt2 : k.kkt; };
+  auto rmet_of = [&](const Kkt& k) { return tn.rmetric == 1 ? k.kkt2 : k.kkt; };
   std::vector<double> k_restart(nb), k_last(nb, HUGE_VAL);
   std::vector<int> inner(nb, 0), total(nb, 0), nrest(nb, 0), done(nb, 0);
   out.assign(nb, gp_solve_stats{});
   for (int b = 0; b < nb; ++b) {
-    const Kkt k = kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b]);
-    k_restart[b] = k.kkt;
-    if (k.kkt <= tol) {
+    const Kkt k = kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]);
+    k_restart[b] = rmet_of(k);
+    if (stop_of(k) <= tol) {
       done[b] = 1;
       p->h_active[batch[b]] = 0;
     }
@@ -749,7 +783,7 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       if (done[b]) continue;
       const int s = batch[b];
       const double* st = p->h_stats.p + (size_t)b * kStats;
-      const Kkt k = kkt_of(p, st, einf[b]);
+      const Kkt k = kkt_of(p, st, einf[b], e2[b], q2[b]);
       total[b] += ce;
       inner[b] += ce;
       out[b].r_pri = k.r_pri;
@@ -770,42 +804,44 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
         k_last[b] = HUGE_VAL;
         continue;
       }
-      if (k.kkt <= tol) {
+      if (stop_of(k) <= tol) {
         done[b] = 1;
         p->h_active[s] = 0;
         --remaining;
         continue;
       }
-      const Tune& tn = p->tune;
-      const bool go = k.kkt <= tn.bsuff * k_restart[b] ||
-                      (k.kkt <= tn.bnec * k_restart[b] && k.kkt > k_last[b]) ||
+      const double m = rmet_of(k);
+      const bool go = m <= tn.bsuff * k_restart[b] || (m <= tn.bnec * k_restart[b] && m > k_last[b]) ||
                       inner[b] >= tn.art * total[b];
       if (p->trace && b == 0)
         fprintf(stderr, "[trace] mode %d it %d kkt %.3e bal %.2e flow %.2e soc %.2e dual %.2e gap %.2e c %.4g cf %.4g dx %.4g dy %.4g restart %d\n",
                 mode, total[b], k.kkt, k.r_bal, k.r_flow, k.r_soc, k.r_dual, k.r_gap, (double)p->h_cw[s],
                 (double)p->h_cwf[s], std::sqrt(st[ST_DX2]), std::sqrt(st[ST_DY2]), (int)go);
-      k_last[b] = k.kkt;
+      k_last[b] = m;
       if (go) {
         const double dx = std::sqrt(st[ST_DX2]), dy = std::sqrt(st[ST_DY2]);
         const double c = p->h_cw[s];
         double cn = c;
-        if (tn.rule == 0) {
+        const int rule = (mode == 1 && tn.arule >= 0) ? tn.arule : tn.rule;
+        if (rule == 0) {
           if (dx > 1e-12 && dy > 1e-12 && std::isfinite(dx) && std::isfinite(dy))
             cn = std::exp(tn.pw_theta * std::log(dy / dx) + (1.0 - tn.pw_theta) * std::log(c));
         } else {
-          const double f = std::sqrt(std::max(k.r_bal, 1e-16) / std::max(std::max(k.r_dual, k.r_gap), 1e-16));
+          const double num = rule == 3 ? std::max(k.r_bal, k.r_soc) : k.r_bal;
+          const double den = rule == 3 ? k.r_gap : std::max(k.r_dual, k.r_gap);
+          const double f = std::pow(std::max(num, 1e-16) / std::max(den, 1e-16), tn.gain);
           cn = c * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
         }
         p->h_cw[s] = (float)std::min(std::max(cn, 1e-6), 1e8);
         if (tn.flow_rule == 1) {
-          const double f = std::sqrt(std::max(k.r_flow, 1e-16) / std::max(k.r_dual, 1e-16));
+          const double f = std::pow(std::max(k.r_flow, 1e-16) / std::max(k.r_dual, 1e-16), tn.gain);
           const double m = p->h_cwf[s] * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
           p->h_cwf[s] = (float)std::min(std::max(m, 1e-4), 1e4);
         }
         p->h_restart[s] = 1;
         any_restart = true;
         inner[b] = 0;
-        k_restart[b] = k.kkt;
+        k_restart[b] = m;
         k_last[b] = HUGE_VAL;
         ++nrest[b];
       }
@@ -1134,30 +1170,29 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
     }
     upload_control(p);
     HIPCHK(hipStreamSynchronize(st));
+    // the timed sweeps advance the iteration state (x, y) only; the stored
+    // solution (xhat, yhat) is written at check iterations, which these are not
     Args a = make_args(p, 0);
-    std::vector<hipEvent_t> ev(4 * iters);
+    hipEvent_t ev[4];
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     const int bs = block_size(p);
-    for (int j = 0; j < iters; ++j) {
-      HIPCHK(hipEventRecord(ev[4 * j], st));
-      HIPCHK(launch_dual(a, bs, j, 0, p->max_T, st));
-      HIPCHK(hipEventRecord(ev[4 * j + 1], st));
-      HIPCHK(hipEventRecord(ev[4 * j + 2], st));
-      HIPCHK(launch_primal(a, bs, j, 0, st));
-      HIPCHK(hipEventRecord(ev[4 * j + 3], st));
-    }
+    // back-to-back launches of one kernel between two events: the mean is the
+    // kernel's own duration (no event gaps)
+    HIPCHK(launch_dual(a, bs, 0, 0, p->max_T, st, 1));  // untimed warm launch
+    HIPCHK(hipEventRecord(ev[0], st));
+    for (int j = 0; j < iters; ++j) HIPCHK(launch_dual(a, bs, j, 0, p->max_T, st, 1));
+    HIPCHK(hipEventRecord(ev[1], st));
+    HIPCHK(launch_primal(a, bs, 0, 0, st, 1));
+    HIPCHK(hipEventRecord(ev[2], st));
+    for (int j = 0; j < iters; ++j) HIPCHK(launch_primal(a, bs, j, 0, st, 1));
+    HIPCHK(hipEventRecord(ev[3], st));
     HIPCHK(hipStreamSynchronize(st));
-    double sd = 0, sp = 0;
-    for (int j = 0; j < iters; ++j) {
-      float a1 = 0, a2 = 0;
-      HIPCHK(hipEventElapsedTime(&a1, ev[4 * j], ev[4 * j + 1]));
-      HIPCHK(hipEventElapsedTime(&a2, ev[4 * j + 2], ev[4 * j + 3]));
-      sd += a1;
-      sp += a2;
-    }
+    float t1 = 0, t2 = 0;
+    HIPCHK(hipEventElapsedTime(&t1, ev[0], ev[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev[2], ev[3]));
     for (auto& e : ev) (void)hipEventDestroy(e);
-    *ms_dual = sd / iters;
-    *ms_primal = sp / iters;
+    *ms_dual = t1 / iters;
+    *ms_primal = t2 / iters;
     return GP_OK;
   });
 }

@@ -44,7 +44,7 @@ def _check_scenario(case, plan, s, eta, cost, stats, omega=0.0, check_grad=True)
     x, y = plan.solution(s)
     assert stats["status"] == 0, stats
     assert stats["kkt"] <= TOL
-    res = D.kkt_residual(qp, x.astype(np.float64), y.astype(np.float64))
+    res = D.kkt_residual(qp, x.astype(np.float64), y)
     assert res["kkt"] <= KKT_SLACK * TOL, res
     gap = abs(cost - sol.obj) / max(1.0, abs(sol.obj))
     assert gap <= TOL, (cost, sol.obj, gap)
@@ -206,7 +206,7 @@ def test_full_size_certificate_on_two_scenarios():
         for s in range(2):
             x, y = p.solution(s)
             qp = D.assemble(cs, s, eta)
-            res = D.kkt_residual(qp, x.astype(np.float64), y.astype(np.float64))
+            res = D.kkt_residual(qp, x.astype(np.float64), y)
             assert res["kkt"] <= KKT_SLACK * TOL, res
             # weak duality bounds the objective gap by the certified gap
             assert (res["P"] - res["D"]) <= TOL * (1 + abs(res["P"]))
