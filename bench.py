@@ -146,11 +146,12 @@ def summarize(stats_csv, fetch_csv, write_csv, pmc_line, workload_id, commands):
             "| kernel | FETCH KiB | WRITE KiB | traffic bytes (scaled) | algorithmic bytes |",
             "|---|---|---|---|---|"]
     rows = []
-    for kern, alg in (("k_primal", info["primal"]), ("k_dual", info["dual"])):
-        pre = f"void gp::{kern}<256, 1>"
+    sfx = "_q" if info.get("variant") == 2 else ""
+    for kern, alg in (("k_primal" + sfx, info["primal"]), ("k_dual" + sfx, info["dual"])):
+        pre = f"void gp::{kern}<{info.get('block', 256)}, 1>"
         f_, w_ = avg(pre, "FETCH_SIZE"), avg(pre, "WRITE_SIZE")
         traffic = f_ * 1024 * fr + w_ * 1024 * fw
-        out.append(f"| `{kern}<256, 1>` | {f_:.0f} | {w_:.0f} | {traffic:.0f} | {alg} |")
+        out.append(f"| `{pre[8:]}` | {f_:.0f} | {w_:.0f} | {traffic:.0f} | {alg} |")
         rows.append((kern, traffic))
     out += ["", "Table read by bench.py (valid while the kernel source hash matches):", "",
             "| key | bytes_per_launch | source_hash |", "|---|---|---|"]
@@ -195,6 +196,7 @@ def main():
         plan = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
         plan.solve(eta, scen, warm=0)
         md, mp = plan.time_sweeps(scen, 10)
+        tb, tv, tce, _ = plan.tuning()
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1.0)
@@ -205,7 +207,7 @@ def main():
         assert float(total) == float(1 << 28)
         ab = algorithmic_bytes(case, scen)
         print(json.dumps({"pmc_run": WORKLOADS[args.config], "ms_dual": md, "ms_primal": mp,
-                          "copy_bytes": 1 << 30, **ab}), flush=True)
+                          "block": tb, "variant": tv, "copy_bytes": 1 << 30, **ab}), flush=True)
         plan.close()
         return
     plan = gridplan.Plan(case, gridplan.options(), stream=gridplan.current_stream())
@@ -234,17 +236,21 @@ def main():
 
     # dominant kernel: HIP-event durations of the two sweeps on the plan's stream
     md, mp = plan.time_sweeps(scen, args.sweep_iters)
+    tb, tv, tce, _ = plan.tuning()
+    sfx = "_q" if tv == 2 else ""
     ab = algorithmic_bytes(case, scen)
     if mp >= md:
-        kname, ms, nbytes = "k_primal", mp, ab["primal"]
+        kname, ms, nbytes = "k_primal" + sfx, mp, ab["primal"]
     else:
-        kname, ms, nbytes = "k_dual", md, ab["dual"]
+        kname, ms, nbytes = "k_dual" + sfx, md, ab["dual"]
     achieved = nbytes / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(kname, args.config),
             "bytes_per_launch": nbytes, "ms_per_launch": round(ms, 5),
-            "other_kernel_ms": round(md if kname == "k_primal" else mp, 5)}
+            "other_kernel_ms": round(md if kname.startswith("k_primal") else mp, 5),
+            "launch": {"block": tb, "form": "work queue" if tv == 2 else "tile grid",
+                       "iterations_per_replay": tce}}
     plan.close()
 
     out = {

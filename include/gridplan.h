@@ -100,13 +100,17 @@ typedef struct {
  * the defaults given in brackets. */
 typedef struct {
   double tol;            /* relative KKT residual target [1e-4] */
-  int32_t max_iter;      /* per solve [200000] */
-  int32_t check_every;   /* iterations between convergence checks [64] */
-  int32_t block;         /* threads per block; 0 = tuned table [0] */
+  int32_t max_iter;      /* per solve [400000] */
+  int32_t check_every;   /* iterations per graph replay and convergence
+                            check; 0 = chosen by the autotuner from
+                            {32, 64, 128} [0] */
+  int32_t block;         /* threads per block (64/128/256/512); 0 = tuned */
   int32_t no_graph;      /* 1 = launch eagerly instead of hipGraph replay */
   double rho0;           /* initial primal weight [10] */
   int32_t verbose;       /* 1 = progress lines on stderr */
-  int32_t reserved[7];
+  int32_t variant;       /* sweep form: 0 tuned, 1 one block per tile,
+                            2 persistent work queue */
+  int32_t reserved[6];
 } gp_options;
 
 /* Per-scenario solve statistics. */
@@ -181,6 +185,14 @@ int dispatch_set_start(gp_plan* p, int32_t s, const float* x, const double* y);
  * Leaves the stored solutions untouched. */
 int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters, double* ms_dual,
                      double* ms_primal);
+
+/* The sweep configuration in use (set by the autotuner on the first solve
+ * of a scenario list unless fixed by the options): threads per block, form
+ * (1 one block per tile, 2 persistent work queue), iterations per graph
+ * replay, and (nullable) the tuner's measured ms per iteration,
+ * [form][block 128, 256, 512], 0 where not measured. */
+int plan_tuning(const gp_plan* p, int32_t* block, int32_t* variant, int32_t* check_every,
+                double* ms_table);
 
 /* Number of capacities K and scenarios S of a plan. */
 int plan_sizes(const gp_plan* p, int64_t* K, int32_t* S);

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "gp_device.h"
 
 namespace gp {
@@ -95,11 +97,10 @@ __device__ __forceinline__ void dual_update(const Args& a, int64_t row, double s
   if (check) a.yhat[row] = yh;
 }
 
-// TAG only separates the instantiation that plan_time_sweeps launches (so a
-// profiler lists the timed launches on their own); the code is identical.
-template <int BS, int TAG>
-__global__ __launch_bounds__(BS) void k_dual(Args a, int j, int check) {
-  const int tix = remap_xcd(blockIdx.x, gridDim.x);
+// One row tile of the dual sweep.  sres: LDS of at least T floats.  Every
+// thread of the block must call it (the SOC-chain branch synchronises).
+template <int BS>
+__device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int check, float* sres) {
   const Tile tl = a.rtiles[tix];
   const int s = tl.scen;
   if (!a.active[s]) return;
@@ -114,7 +115,6 @@ __global__ __launch_bounds__(BS) void k_dual(Args a, int j, int check) {
   if (tl.cls == RC_SOC) {
     // one battery chain per block: residuals to LDS, then the circulant
     // inverse of the chain block (C R^-1 C') applied as a short convolution
-    extern __shared__ float sres[];
     const int kb = tl.start;
     for (int t = threadIdx.x; t < T; t += BS) sres[t] = soc_residual(nt, xs, T, kb, t, a.eff);
     __syncthreads();
@@ -158,6 +158,14 @@ __global__ __launch_bounds__(BS) void k_dual(Args a, int j, int check) {
     dual_update(a, sc.yoff + (int64_t)nt.N * TT + i, c * (double)a.cwf[s] * (double)a.w.sig_flow * (double)res,
                 lam, check);
   }
+}
+
+// TAG only separates the instantiation that plan_time_sweeps launches (so a
+// profiler lists the timed launches on their own); the code is identical.
+template <int BS, int TAG>
+__global__ __launch_bounds__(BS) void k_dual(Args a, int j, int check) {
+  extern __shared__ float sres[];
+  dual_tile<BS>(a, remap_xcd(blockIdx.x, gridDim.x), j, check, sres);
 }
 
 // ----------------------------------------------------------------------------
@@ -204,9 +212,8 @@ __device__ __forceinline__ double angle_ety(const Args& a, const NetDev& nt, con
   return ey;
 }
 
-template <int BS, int TAG>
-__global__ __launch_bounds__(BS) void k_primal(Args a, int j, int check) {
-  const int tix = remap_xcd(blockIdx.x, gridDim.x);
+// One variable tile of the primal sweep.
+__device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int check) {
   const Tile tl = a.vtiles[tix];
   const int s = tl.scen;
   if (!a.active[s]) return;
@@ -263,6 +270,59 @@ __global__ __launch_bounds__(BS) void k_primal(Args a, int j, int check) {
       break;
     }
   }
+}
+
+template <int BS, int TAG>
+__global__ __launch_bounds__(BS) void k_primal(Args a, int j, int check) {
+  primal_tile(a, remap_xcd(blockIdx.x, gridDim.x), j, check);
+}
+
+// ----------------------------------------------------------------------------
+// persistent work-queue form of the two sweeps
+// ----------------------------------------------------------------------------
+
+// A fixed grid of resident blocks takes tiles from a 64-bit counter until the
+// queue is drained (every block exits once a fetch passes the tile count); the
+// last block to leave resets the counter pair for the next launch.
+__device__ __forceinline__ void queue_done(unsigned long long* qc, unsigned int* qd) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(qd, 1u) == gridDim.x - 1) {
+      atomicExch(qc, 0ULL);
+      atomicExch(qd, 0u);
+    }
+  }
+}
+
+template <int BS, int TAG>
+__global__ __launch_bounds__(BS) void k_dual_q(Args a, int j, int check, unsigned long long* qc,
+                                               unsigned int* qd) {
+  extern __shared__ float sres[];
+  __shared__ long long cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = (long long)atomicAdd(qc, 1ULL);
+    __syncthreads();
+    const long long t = cur;
+    if (t >= a.nrt) break;
+    dual_tile<BS>(a, (int)t, j, check, sres);
+    __syncthreads();
+  }
+  queue_done(qc, qd);
+}
+
+template <int BS, int TAG>
+__global__ __launch_bounds__(BS) void k_primal_q(Args a, int j, int check, unsigned long long* qc,
+                                                 unsigned int* qd) {
+  __shared__ long long cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = (long long)atomicAdd(qc, 1ULL);
+    __syncthreads();
+    const long long t = cur;
+    if (t >= a.nvt) break;
+    primal_tile(a, (int)t, j, check);
+    __syncthreads();
+  }
+  queue_done(qc, qd);
 }
 
 // ----------------------------------------------------------------------------
@@ -730,8 +790,20 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
     default: call(256); break;   \
   }
 
-hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st, int timed) {
+// variant 0: one block per tile; variant 1: persistent work queue over
+// `qblocks` resident blocks (q: two counter pairs, dual then primal)
+hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st, int timed,
+                       int variant, int qblocks, unsigned long long* qc, unsigned int* qd) {
   const size_t sh = (size_t)max_T * sizeof(float);
+  if (variant == 1) {
+    const int g = std::min(qblocks, a.nrt);
+#define L_(B)                                                                                   \
+  if (timed) hipLaunchKernelGGL((k_dual_q<B, 1>), dim3(g), dim3(B), sh, st, a, j, check, qc, qd); \
+  else hipLaunchKernelGGL((k_dual_q<B, 0>), dim3(g), dim3(B), sh, st, a, j, check, qc, qd)
+    GP_DISPATCH_BS(bs, L_)
+#undef L_
+    return hipGetLastError();
+  }
 #define L_(B)                                                                                     \
   if (timed) hipLaunchKernelGGL((k_dual<B, 1>), dim3(a.nrt), dim3(B), sh, st, a, j, check);        \
   else hipLaunchKernelGGL((k_dual<B, 0>), dim3(a.nrt), dim3(B), sh, st, a, j, check)
@@ -740,7 +812,17 @@ hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed) {
+hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed,
+                         int variant, int qblocks, unsigned long long* qc, unsigned int* qd) {
+  if (variant == 1) {
+    const int g = std::min(qblocks, a.nvt);
+#define L_(B)                                                                                    \
+  if (timed) hipLaunchKernelGGL((k_primal_q<B, 1>), dim3(g), dim3(B), 0, st, a, j, check, qc, qd); \
+  else hipLaunchKernelGGL((k_primal_q<B, 0>), dim3(g), dim3(B), 0, st, a, j, check, qc, qd)
+    GP_DISPATCH_BS(bs, L_)
+#undef L_
+    return hipGetLastError();
+  }
 #define L_(B)                                                                                     \
   if (timed) hipLaunchKernelGGL((k_primal<B, 1>), dim3(a.nvt), dim3(B), 0, st, a, j, check);       \
   else hipLaunchKernelGGL((k_primal<B, 0>), dim3(a.nvt), dim3(B), 0, st, a, j, check)

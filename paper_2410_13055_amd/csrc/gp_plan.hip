@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,8 +19,10 @@
 #include "gp_device.h"
 
 namespace gp {
-hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st, int timed = 0);
-hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed = 0);
+hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st, int timed,
+                       int variant, int qblocks, unsigned long long* qc, unsigned int* qd);
+hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed,
+                         int variant, int qblocks, unsigned long long* qc, unsigned int* qd);
 hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st);
 hipError_t launch_reset(const Args& a, int bs, int cold, hipStream_t st);
 hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st);
@@ -190,6 +193,15 @@ struct gp_plan {
   DevBuf<int64_t> d_goff;
   PinBuf<double> h_gpart;
   int64_t gpart_n = 0;
+  // sweep launch configuration (tuned per batch unless fixed by options)
+  int bs = 256;          // threads per block (and items per tile)
+  int variant = 0;       // 0: one block per tile, 1: persistent work queue
+  int ce = 64;           // iterations per graph replay / convergence check
+  int qblocks = 2048;    // resident blocks of the work-queue form
+  std::vector<int> tuned_batch;
+  double tune_ms[2][3] = {{0}};  // measured ms per iteration [variant][bs 128/256/512]
+  DevBuf<unsigned long long> d_qc;  // work-queue counters: dual, primal
+  DevBuf<unsigned int> d_qd;
   // graph of one iteration chunk
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -210,7 +222,7 @@ struct gp_plan {
 
 namespace {
 
-int block_size(const gp_plan* p) { return p->opt.block > 0 ? p->opt.block : 256; }
+int block_size(const gp_plan* p) { return p->opt.block > 0 ? p->opt.block : p->bs; }
 
 // SOC chain block (C R^-1 C') of one battery is circulant with diagonal
 // (3 + eff^2)/ws and off-diagonals -1/ws (cyclic); its inverse is circulant
@@ -500,6 +512,24 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->h_kbase.alloc(p->S);
   p->h_active.alloc(p->S);
   p->h_restart.alloc(p->S);
+  // zero state: sweeps (and the tuner) never read uninitialised memory
+  HIPCHK(hipMemsetAsync(p->d_x.p, 0, xoff * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(p->d_x0.p, 0, xoff * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(p->d_xhat.p, 0, xoff * sizeof(float), st));
+  HIPCHK(hipMemsetAsync(p->d_y.p, 0, yoff * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_y0.p, 0, yoff * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_ybar.p, 0, yoff * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_yhat.p, 0, yoff * sizeof(double), st));
+  p->d_qc.alloc(2);
+  p->d_qd.alloc(2);
+  HIPCHK(hipMemsetAsync(p->d_qc.p, 0, 2 * sizeof(unsigned long long), st));
+  HIPCHK(hipMemsetAsync(p->d_qd.p, 0, 2 * sizeof(unsigned int), st));
+  {
+    int dev = 0, ncu = 256;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    p->qblocks = std::max(1, ncu) * 8;
+  }
   p->has_solution.assign(p->S, 0);
   p->last_cw.assign(p->S, 0.f);
   p->last_cwf.assign(p->S, 1.f);
@@ -581,8 +611,8 @@ void drop_graph(gp_plan* p) {
 
 // tiles of the batch: per scenario, variable tiles [gens | lines | nodes |
 // batteries] and row tiles [balance | flow | one per battery chain]
-void build_tiles(gp_plan* p, const std::vector<int>& batch) {
-  if (batch == p->batch && p->nvt > 0) return;
+void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) {
+  if (!force && batch == p->batch && p->nvt > 0) return;
   const int bs = block_size(p);
   std::vector<Tile> vt, rt;
   std::vector<int32_t> ranges;
@@ -640,28 +670,33 @@ void upload_control(gp_plan* p) {
 
 // one chunk: check_every iterations (the last one writes (xhat, yhat)) and
 // the FP64 statistics of that pair, then the statistics copied to the host
-void enqueue_chunk(gp_plan* p, const Args& a, int ce) {
+void launch_iteration(gp_plan* p, const Args& a, int j, int check, int timed) {
   hipStream_t st = p->stream;
   const int bs = block_size(p);
-  for (int j = 0; j < ce; ++j) {
-    HIPCHK(launch_dual(a, bs, j, j == ce - 1, p->max_T, st));
-    HIPCHK(launch_primal(a, bs, j, j == ce - 1, st));
-  }
+  HIPCHK(launch_dual(a, bs, j, check, p->max_T, st, timed, p->variant, p->qblocks, p->d_qc.p, p->d_qd.p));
+  HIPCHK(launch_primal(a, bs, j, check, st, timed, p->variant, p->qblocks, p->d_qc.p + 1, p->d_qd.p + 1));
+}
+
+// write_check = 0 (tuning only) leaves the stored (xhat, yhat) untouched
+void enqueue_chunk(gp_plan* p, const Args& a, int ce, int write_check = 1) {
+  hipStream_t st = p->stream;
+  const int bs = block_size(p);
+  for (int j = 0; j < ce; ++j) launch_iteration(p, a, j, write_check && j == ce - 1, 0);
   HIPCHK(launch_check(a, bs, (int)p->batch.size(), st));
   HIPCHK(hipMemcpyAsync(p->h_stats.p, a.stats, p->batch.size() * kStats * sizeof(double),
                         hipMemcpyDeviceToHost, st));
 }
 
-void run_chunk(gp_plan* p, const Args& a, int ce, int mode) {
+void run_chunk(gp_plan* p, const Args& a, int ce, int mode, int write_check = 1) {
   hipStream_t st = p->stream;
   if (p->opt.no_graph) {
-    enqueue_chunk(p, a, ce);
+    enqueue_chunk(p, a, ce, write_check);
   } else {
     if (!p->gexec || p->graph_mode != mode) {
       drop_graph(p);
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       try {
-        enqueue_chunk(p, a, ce);
+        enqueue_chunk(p, a, ce, write_check);
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(st, &g);
@@ -683,6 +718,91 @@ void run_check_only(gp_plan* p, const Args& a) {
   HIPCHK(hipMemcpyAsync(p->h_stats.p, a.stats, p->batch.size() * kStats * sizeof(double),
                         hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+}
+
+// Autotuner: for the batch's tile tables, time the two sweeps in both forms
+// (one block per tile, persistent work queue) at 128, 256 and 512 threads,
+// keep the fastest, then pick the iterations per graph replay as the smallest
+// of {32, 64, 128} whose replay costs at most 5 % more per iteration than the
+// cheapest (a shorter chunk checks convergence and restarts more often).
+// Options that fix a choice (block, variant, check_every) are respected.
+void autotune(gp_plan* p, const std::vector<int>& batch) {
+  const bool fix_bs = p->opt.block > 0, fix_ce = p->opt.check_every > 0;
+  const int fix_var = p->opt.variant;  // 0 tuned, 1 tiled, 2 work queue
+  if (fix_var) p->variant = fix_var - 1;
+  if ((fix_bs && fix_var && fix_ce) || batch == p->tuned_batch) return;
+  hipStream_t st = p->stream;
+  std::fill(p->h_active.p, p->h_active.p + p->S, 0);
+  std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+  for (int s : batch) {
+    p->h_active[s] = 1;
+    p->h_kbase[s] = 0;
+    p->h_cw[s] = 10.f;
+    p->h_cwf[s] = 1.f;
+  }
+  upload_control(p);
+  HIPCHK(hipStreamSynchronize(st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int bss[3] = {128, 256, 512};
+  double best = HUGE_VAL;
+  int best_bs = p->bs, best_v = p->variant;
+  for (int ib = 0; ib < 3; ++ib) {
+    if (fix_bs && bss[ib] != p->opt.block) continue;
+    p->bs = bss[ib];
+    build_tiles(p, batch, true);
+    const Args a = make_args(p, 0);
+    for (int v = 0; v < 2; ++v) {
+      if (fix_var && v != fix_var - 1) continue;
+      p->variant = v;
+      for (int j = 0; j < 2; ++j) launch_iteration(p, a, j, 0, 0);
+      const int n = 8;
+      HIPCHK(hipEventRecord(e0, st));
+      for (int j = 0; j < n; ++j) launch_iteration(p, a, j, 0, 0);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      p->tune_ms[v][ib] = ms / n;
+      if (ms / n < best) {
+        best = ms / n;
+        best_bs = bss[ib];
+        best_v = v;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->bs = best_bs;
+  p->variant = best_v;
+  build_tiles(p, batch, true);
+  if (!fix_ce) {
+    const Args a = make_args(p, 0);
+    const int ces[3] = {32, 64, 128};
+    double per[3];
+    for (int q = 0; q < 3; ++q) {
+      p->ce = ces[q];
+      drop_graph(p);
+      run_chunk(p, a, ces[q], 0, 0);  // capture + first replay
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int r = 0; r < 2; ++r) run_chunk(p, a, ces[q], 0, 0);
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      per[q] = sec / (2.0 * ces[q]);
+    }
+    const double mn = std::min(per[0], std::min(per[1], per[2]));
+    p->ce = ces[2];
+    for (int q = 0; q < 3; ++q)
+      if (per[q] <= 1.05 * mn) {
+        p->ce = ces[q];
+        break;
+      }
+  }
+  drop_graph(p);
+  p->tuned_batch = batch;
+  if (p->opt.verbose)
+    fprintf(stderr, "[gridplan] tuned: block %d, %s, %d iterations per replay\n", p->bs,
+            p->variant ? "work queue" : "tile grid", p->ce);
 }
 
 struct Kkt {
@@ -719,8 +839,8 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   const int nb = (int)batch.size();
   Args a = make_args(p, mode);
   a.omega = (float)omega;
-  const int ce = std::max(2, p->opt.check_every > 0 ? p->opt.check_every : 64);
-  const int max_iter = p->opt.max_iter > 0 ? p->opt.max_iter : 200000;
+  const int ce = std::max(2, p->opt.check_every > 0 ? p->opt.check_every : p->ce);
+  const int max_iter = p->opt.max_iter > 0 ? p->opt.max_iter : 400000;
   const double tol = p->opt.tol > 0 ? p->opt.tol : 1e-4;
   const float c0 = (float)(p->opt.rho0 > 0 ? p->opt.rho0 : 10.0);
   std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
@@ -909,6 +1029,7 @@ int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, i
   for (int64_t j = 0; j < p->K; ++j) ef[j] = (float)eta[j];
   HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
   build_tiles(p, batch);
+  autotune(p, batch);
   bool all_warm = warm == 1;
   for (int s : batch) all_warm = all_warm && p->has_solution[s];
   std::vector<double> einf;
@@ -1039,6 +1160,7 @@ int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void
         fail(GP_EINVAL, "negative option");
       if (opt->block != 0 && opt->block != 64 && opt->block != 128 && opt->block != 256 && opt->block != 512)
         fail(GP_EINVAL, "block must be 0, 64, 128, 256 or 512");
+      if (opt->variant < 0 || opt->variant > 2) fail(GP_EINVAL, "variant must be 0, 1 or 2");
     }
     p = new gp_plan();
     if (opt) p->opt = *opt;
@@ -1178,13 +1300,16 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
     const int bs = block_size(p);
     // back-to-back launches of one kernel between two events: the mean is the
     // kernel's own duration (no event gaps)
-    HIPCHK(launch_dual(a, bs, 0, 0, p->max_T, st, 1));  // untimed warm launch
+    const int v = p->variant;
+    unsigned long long* qc = p->d_qc.p;
+    unsigned int* qd = p->d_qd.p;
+    HIPCHK(launch_dual(a, bs, 0, 0, p->max_T, st, 1, v, p->qblocks, qc, qd));  // untimed warm launch
     HIPCHK(hipEventRecord(ev[0], st));
-    for (int j = 0; j < iters; ++j) HIPCHK(launch_dual(a, bs, j, 0, p->max_T, st, 1));
+    for (int j = 0; j < iters; ++j) HIPCHK(launch_dual(a, bs, j, 0, p->max_T, st, 1, v, p->qblocks, qc, qd));
     HIPCHK(hipEventRecord(ev[1], st));
-    HIPCHK(launch_primal(a, bs, 0, 0, st, 1));
+    HIPCHK(launch_primal(a, bs, 0, 0, st, 1, v, p->qblocks, qc + 1, qd + 1));
     HIPCHK(hipEventRecord(ev[2], st));
-    for (int j = 0; j < iters; ++j) HIPCHK(launch_primal(a, bs, j, 0, st, 1));
+    for (int j = 0; j < iters; ++j) HIPCHK(launch_primal(a, bs, j, 0, st, 1, v, p->qblocks, qc + 1, qd + 1));
     HIPCHK(hipEventRecord(ev[3], st));
     HIPCHK(hipStreamSynchronize(st));
     float t1 = 0, t2 = 0;
@@ -1195,6 +1320,18 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
     *ms_primal = t2 / iters;
     return GP_OK;
   });
+}
+
+int plan_tuning(const gp_plan* p, int32_t* block, int32_t* variant, int32_t* check_every,
+                double* ms_table) {
+  if (!p) return GP_EINVAL;
+  if (block) *block = p->opt.block > 0 ? p->opt.block : p->bs;
+  if (variant) *variant = p->variant + 1;
+  if (check_every) *check_every = p->opt.check_every > 0 ? p->opt.check_every : p->ce;
+  if (ms_table)
+    for (int v = 0; v < 2; ++v)
+      for (int b = 0; b < 3; ++b) ms_table[3 * v + b] = p->tune_ms[v][b];
+  return GP_OK;
 }
 
 int plan_sizes(const gp_plan* p, int64_t* K, int32_t* S) {

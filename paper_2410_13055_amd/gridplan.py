@@ -20,8 +20,8 @@ GP_OK, GP_ENOTCONVERGED = 0, 1
 GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ESTATE = -1, -2, -3, -4
 
 EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "plan_step",
-           "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_sizes",
-           "plan_free", "plan_last_error")
+           "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_tuning",
+           "plan_sizes", "plan_free", "plan_last_error")
 
 
 class GridplanError(RuntimeError):
@@ -59,7 +59,7 @@ class gp_case_desc(C.Structure):
 class gp_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("block", C.c_int32), ("no_graph", C.c_int32), ("rho0", C.c_double),
-                ("verbose", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("verbose", C.c_int32), ("variant", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class gp_solve_stats(C.Structure):
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.plan_time_sweeps.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_int32,
                                      P(C.c_double), P(C.c_double)]
     lib.plan_time_sweeps.restype = C.c_int
+    lib.plan_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_double)]
+    lib.plan_tuning.restype = C.c_int
     lib.plan_sizes.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32)]
     lib.plan_sizes.restype = C.c_int
     lib.plan_free.argtypes = [C.c_void_p]
@@ -156,9 +158,10 @@ class _Descriptor:
                                  float(case.r), float(case.lambda_u), float(case.eff), float(case.hours))
 
 
-def options(tol=1e-4, max_iter=0, check_every=0, block=0, no_graph=0, rho0=0.0, verbose=0):
+def options(tol=1e-4, max_iter=0, check_every=0, block=0, no_graph=0, rho0=0.0, verbose=0,
+            variant=0):
     return gp_options(float(tol), int(max_iter), int(check_every), int(block), int(no_graph),
-                      float(rho0), int(verbose))
+                      float(rho0), int(verbose), int(variant))
 
 
 def current_stream():
@@ -273,6 +276,13 @@ class Plan:
         self._check(self.lib.plan_time_sweeps(self.h, _ptr(idx, C.c_int32), idx.shape[0], int(iters),
                                               C.byref(md), C.byref(mp)), allow_nc=False)
         return md.value, mp.value
+
+    def tuning(self):
+        """(block, variant, check_every, ms table [2 forms x 3 block sizes])."""
+        b, v, c = C.c_int32(), C.c_int32(), C.c_int32()
+        tab = np.zeros(6)
+        self.lib.plan_tuning(self.h, C.byref(b), C.byref(v), C.byref(c), _ptr(tab, C.c_double))
+        return int(b.value), int(v.value), int(c.value), tab.reshape(2, 3)
 
     def set_start(self, s: int, x, y=None):
         x = np.ascontiguousarray(x, np.float32)

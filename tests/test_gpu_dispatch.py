@@ -135,7 +135,7 @@ def test_emissions_gradient_small_network():
 def test_batch_composition_does_not_change_results():
     cs = cases.small_geo(n_nodes=12, G=30, B=3, T=24, S=3, seed=7)
     eta = _eta(cs, 4)
-    with _plan(cs) as p:
+    with _plan(cs, block=256, variant=1, check_every=64) as p:
         p.solve(eta, [0, 1, 2])
         xa, ya = p.solution(1)
         p.solve(eta, [1])
@@ -150,10 +150,11 @@ def test_batch_composition_does_not_change_results():
 def test_graph_replay_equals_eager():
     cs = cases.small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7)
     eta = _eta(cs, 4)
-    with _plan(cs) as p:
+    fixed = dict(block=256, variant=1, check_every=64)   # no tuner: same launches
+    with _plan(cs, **fixed) as p:
         p.solve(eta, [0, 1])
         xg, yg = p.solution(0)
-    with _plan(cs, no_graph=1) as p:
+    with _plan(cs, no_graph=1, **fixed) as p:
         p.solve(eta, [0, 1])
         xe, ye = p.solution(0)
     np.testing.assert_array_equal(xg, xe)
