@@ -110,7 +110,12 @@ typedef struct {
   int32_t verbose;       /* 1 = progress lines on stderr */
   int32_t variant;       /* sweep form: 0 tuned, 1 one block per tile,
                             2 persistent work queue */
-  int32_t reserved[6];
+  int32_t accept_warm;   /* 1 = take every warm start as given: no
+                            residual screen, no stall limit [0] */
+  int32_t stall_pct;     /* stall limit of a warm start, in percent of the
+                            iterations of the network's last converged
+                            cold solve; 0 = 100 [0] */
+  int32_t reserved[4];
 } gp_options;
 
 /* Per-scenario solve statistics. */
@@ -118,7 +123,10 @@ typedef struct {
   int32_t iters;     /* iterations used */
   int32_t restarts;  /* restarts taken */
   int32_t status;    /* 0 converged, 1 iteration limit */
-  int32_t pad;
+  int32_t start;     /* 0 cold, 1 warm, 2 warm start screened out (its
+                        KKT residual was above 100 times the cold
+                        start's), 3 warm start abandoned for a cold
+                        start after the stall limit */
   double r_pri, r_dual, r_gap, kkt;  /* relative KKT residual parts (FP64) */
   double cost;       /* c_s(x) at the returned point */
   double emis;       /* sum emis_g p at the returned point, t */
@@ -141,8 +149,16 @@ int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void
  *   r_dual = ||(E'y - q - r x)_free||_inf / (1 + ||q||_inf),
  *   r_gap = |P(x) - D(y)| / (1 + max(|P(x)|, |D(y)|)), D the exact dual
  *   function, all in FP64.
- * scen: [nb] distinct scenario indices.  warm_mode: 0 cold start, 1 start
- * from each scenario's last solution.  cost_out: [nb] c_s(x) (nullable).
+ * scen: [nb] distinct scenario indices.  warm_mode: 0 cold start (x = 0,
+ * y = 0), 1 start from each scenario's stored point: its last solution, or
+ * the point plan_start_from_prediction seeded; scenarios without a stored
+ * point start cold.  Per scenario, a warm start whose KKT residual (the
+ * stopping norm) exceeds 100 times the cold start's is replaced by the cold
+ * start (stats.start = 2), and one that has not converged within the
+ * iterations of the last converged cold solve on the same network (times
+ * opt.stall_pct / 100) restarts cold (stats.start = 3; iters counts both
+ * parts).
+ * cost_out: [nb] c_s(x) (nullable).
  * stats_out: [nb] (nullable).  Returns GP_OK, GP_ENOTCONVERGED or an error. */
 int dispatch_solve_batch(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb,
                          int32_t warm_mode, double* cost_out, gp_solve_stats* stats_out);
@@ -193,6 +209,61 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
  * [form][block 128, 256, 512], 0 where not measured. */
 int plan_tuning(const gp_plan* p, int32_t* block, int32_t* variant, int32_t* check_every,
                 double* ms_table);
+
+/* ---- learned warm start (predicted prices and angles seed the solver) ----
+ * Rows are one per (listed scenario, node), scenarios in list order, nodes in
+ * network order; all listed scenarios must share T.  Matrices are row-major
+ * FP32 in DEVICE memory owned by the caller. */
+
+/* Number of rows and the common horizon T of a scenario list. */
+int plan_nn_rows(gp_plan* p, const int32_t* scen, int32_t nb, int64_t* rows, int32_t* T);
+
+/* Features at capacities eta: X_dev [rows x (5T + 3)] = per hour the node's
+ * load, available renewable (zero-cost) capacity, available thermal
+ * capacity, neighbours' load and neighbours' available renewable capacity
+ * (MW/100), then the node's battery capacity, incident line capacity and
+ * thermal nameplate (MW/100). */
+int plan_features(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, float* X_dev);
+
+/* Targets from the stored solutions: Y_dev [rows x 2T] = asinh(price/100)
+ * per hour, then angle/10 per hour. */
+int plan_targets(gp_plan* p, const int32_t* scen, int32_t nb, float* Y_dev);
+
+/* Seed the listed scenarios' next warm_mode = 1 solve from a prediction
+ * P_dev [rows x 2T] in the target encoding: prices become the balance duals,
+ * angles the bus angles, flows the clipped DC flows of those angles,
+ * generators and unserved load their best response to the price, flow duals
+ * the lines' stationarity at that flow, batteries and SOC duals zero. */
+int plan_start_from_prediction(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb,
+                               const float* P_dev);
+
+/* ---- the warm-start network: an MLP with BF16 MFMA GEMMs (FP32 accumulate),
+ * FP32 master weights and Adam.  Layers n_in -> width (x hidden_layers) ->
+ * n_out, ReLU between; parameters flat: all weight matrices ([in x out]
+ * row-major, layer order) then all biases. */
+typedef struct gp_mlp gp_mlp;
+int mlp_init(gp_mlp** out, int32_t n_in, int32_t width, int32_t hidden_layers, int32_t n_out, uint64_t seed,
+             void* hip_stream);
+int mlp_num_params(const gp_mlp* m, int64_t* n);
+int mlp_get_params(gp_mlp* m, float* w_out);       /* host [n] */
+int mlp_set_params(gp_mlp* m, const float* w_in);  /* host [n] */
+/* Y [rows x n_out] = net(X [rows x n_in]); on_device selects device (1) or
+ * host (0) pointers for X and Y. */
+int mlp_forward(gp_mlp* m, const float* X, int64_t rows, int32_t on_device, float* Y);
+/* Mean squared error over all outputs and its parameter gradient (host
+ * [n], nullable). */
+int mlp_loss_grad(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device, double* loss,
+                  float* grad_out);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error. */
+int mlp_adam_step(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device, double lr,
+                  double* loss);
+/* C [M x N] = op(A) op(B) through the same BF16 MFMA kernel (host FP32 in,
+ * rounded to BF16; op = transpose when ta / tb).  A is [M x K] or [K x M],
+ * B [K x N] or [N x K]. */
+int mlp_gemm_test(const float* A, const float* B, float* C, int32_t M, int32_t N, int32_t K, int32_t ta,
+                  int32_t tb);
+void mlp_free(gp_mlp* m);
+const char* mlp_last_error(const gp_mlp* m);
 
 /* Number of capacities K and scenarios S of a plan. */
 int plan_sizes(const gp_plan* p, int64_t* K, int32_t* S);

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgridplan.so")
-SOURCES = ["gp_kernels.hip", "gp_plan.hip"]
+SOURCES = ["gp_kernels.hip", "gp_plan.hip", "gp_mlp.hip"]
 ARCH = os.environ.get("GRIDPLAN_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every HIP object (the compiler

@@ -30,6 +30,7 @@ constexpr int kMaxStats = 5;  // slots [0, kMaxStats) are maxima, the rest sums
 enum VarClass { VC_GEN = 0, VC_LINE = 1, VC_NODE = 2, VC_BATT = 3 };
 // work classes of the dual (row) sweep
 enum RowClass { RC_BAL = 0, RC_FLOW = 1, RC_SOC = 2 };
+enum ResetMode { RESET_WARM = 0, RESET_COLD = 1, RESET_PROBE = 2, RESET_RESTORE = 3 };
 
 struct Tile {
   int32_t scen;   // scenario index

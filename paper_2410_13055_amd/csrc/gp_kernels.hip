@@ -566,9 +566,15 @@ __global__ __launch_bounds__(BS) void k_reduce(Args a) {
 // state reset / restart
 // ----------------------------------------------------------------------------
 
-// mode 0: cold start (zeros), 1: restart from (xhat, yhat) where restart[s]
+// Start / restart of the scenarios with restart[s] set.  The output point is
+// (xhat, yhat); (x0, y0) the anchors; ybar the extrapolated dual.
+//   RESET_WARM    everything from the output point (restart, warm start)
+//   RESET_COLD    everything zero
+//   RESET_PROBE   output point zero, iterate and anchors kept (a check pass
+//                 then measures the cold start's residual)
+//   RESET_RESTORE output point, iterate and dual from the anchors
 template <int BS>
-__global__ __launch_bounds__(BS) void k_reset(Args a, int cold) {
+__global__ __launch_bounds__(BS) void k_reset(Args a, int mode) {
   const bool rows = (int)blockIdx.x >= a.nvt;
   const int tix = rows ? (int)blockIdx.x - a.nvt : (int)blockIdx.x;
   const Tile tl = rows ? a.rtiles[tix] : a.vtiles[tix];
@@ -602,27 +608,38 @@ __global__ __launch_bounds__(BS) void k_reset(Args a, int cold) {
     }
     for (int q = 0; q < nidx; ++q) {
       const int64_t g = sc.xoff + idx[q];
-      const float v = cold ? 0.f : a.xhat[g];
+      if (mode == RESET_PROBE) {
+        a.xhat[g] = 0.f;
+        continue;
+      }
+      const float v = mode == RESET_COLD ? 0.f : mode == RESET_RESTORE ? a.x0[g] : a.xhat[g];
       a.x[g] = v;
       a.x0[g] = v;
       a.xhat[g] = v;
     }
+    return;
+  }
+  int64_t r0, step, n;
+  int first;
+  if (tl.cls == RC_SOC) {
+    // one block per battery chain: threads stride over its hours
+    r0 = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)tl.start * TT;
+    first = threadIdx.x;
+    step = BS;
+    n = T;
   } else {
-    if (tl.cls == RC_SOC) {
-      const int64_t rbase = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)tl.start * TT;
-      for (int t = threadIdx.x; t < T; t += BS) {
-        const double v = cold ? 0.0 : a.yhat[rbase + t];
-        a.y[rbase + t] = v;
-        a.y0[rbase + t] = v;
-        a.ybar[rbase + t] = v;
-        a.yhat[rbase + t] = v;
-      }
-      return;
+    r0 = sc.yoff + (tl.cls == RC_BAL ? 0 : (int64_t)nt.N * TT) + tl.start;
+    first = threadIdx.x;
+    step = BS;
+    n = tl.count;
+  }
+  for (int64_t t = first; t < n; t += step) {
+    const int64_t g = r0 + t;
+    if (mode == RESET_PROBE) {
+      a.yhat[g] = 0.0;
+      continue;
     }
-    if ((int)threadIdx.x >= tl.count) return;
-    const int i = tl.start + threadIdx.x;
-    const int64_t g = sc.yoff + (tl.cls == RC_BAL ? (int64_t)i : (int64_t)nt.N * TT + i);
-    const double v = cold ? 0.0 : a.yhat[g];
+    const double v = mode == RESET_COLD ? 0.0 : mode == RESET_RESTORE ? a.y0[g] : a.yhat[g];
     a.y[g] = v;
     a.y0[g] = v;
     a.ybar[g] = v;
@@ -841,8 +858,8 @@ hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_reset(const Args& a, int bs, int cold, hipStream_t st) {
-#define L_(B) hipLaunchKernelGGL(k_reset<B>, dim3(a.nvt + a.nrt), dim3(B), 0, st, a, cold)
+hipError_t launch_reset(const Args& a, int bs, int mode, hipStream_t st) {
+#define L_(B) hipLaunchKernelGGL(k_reset<B>, dim3(a.nvt + a.nrt), dim3(B), 0, st, a, mode)
   GP_DISPATCH_BS(bs, L_)
 #undef L_
   return hipGetLastError();
@@ -860,6 +877,224 @@ hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev,
   const int64_t threads = ndev * 64;
   const int nblk = (int)((threads + 255) / 256);
   hipLaunchKernelGGL(k_grad<256>, dim3(nblk), dim3(256), 0, st, a, goff, nb, mode_adj);
+  return hipGetLastError();
+}
+
+}  // namespace gp
+
+namespace gp {
+
+// ----------------------------------------------------------------------------
+// learned warm start: node features, training targets, start from prediction
+// ----------------------------------------------------------------------------
+// One row per (batch scenario, node); rowoff[s] = first row of scenario s
+// (-1 when not in the batch).  All scenarios of a batch share T.
+//   features [5T + 3]: own load, renewable (zero-cost) available capacity,
+//     thermal available capacity, neighbours' load, neighbours' renewable
+//     capacity (each [T], MW / 100); battery capacity, incident line
+//     capacity, thermal nameplate (MW / 100)
+//   targets [2T]: asinh(price / 100), angle / 10
+
+__device__ __forceinline__ void node_avail(const Args& a, const NetDev& nt, const ScenDev& sc, int n, int t,
+                                           float& ren, float& thr) {
+  const int e0 = a.term_ptr[nt.tptr_off + n], e1 = a.term_ptr[nt.tptr_off + n + 1];
+  ren = 0.f;
+  thr = 0.f;
+  for (int e = e0; e < e1; ++e) {
+    const int code = a.term[e];
+    if ((code & 3) != TT_GEN) continue;
+    const int g = code >> 2;
+    const float cap = a.avail[sc.aoff + (int64_t)g * sc.T + t] * a.eta[nt.eta_off + g];
+    if (a.gen_cost[nt.gen_off + g] > 0.f) thr += cap;
+    else ren += cap;
+  }
+}
+
+__global__ void k_features(Args a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, float* X) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // thread per (row, t): rows are flattened over the batch
+  const int64_t row = gid / T;
+  const int t = (int)(gid - row * T);
+  // find the batch entry of this row
+  int b = -1;
+  for (int q = 0; q < nb; ++q) {
+    const int s = bscen[q];
+    const int r0 = rowoff[s];
+    const int N = a.net[a.scen[s].net].N;
+    if (row >= r0 && row < r0 + N) {
+      b = q;
+      break;
+    }
+  }
+  if (b < 0) return;
+  const int s = bscen[b];
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int n = (int)(row - rowoff[s]);
+  const int F = 5 * T + 3;
+  float* x = X + row * F;
+  const float sc100 = 0.01f;
+  float ren, thr;
+  node_avail(a, nt, sc, n, t, ren, thr);
+  float nl = 0.f, nren = 0.f, lcap = 0.f;
+  const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int code = a.ang[e];
+    const int l = code >> 1;
+    const int m = (code & 1) ? a.line_to[nt.line_off + l] : a.line_from[nt.line_off + l];
+    nl += a.load[sc.doff + (int64_t)m * T + t];
+    float r2, t2;
+    node_avail(a, nt, sc, m, t, r2, t2);
+    nren += r2;
+    lcap += a.eta[nt.eta_off + nt.G + l];
+  }
+  x[t] = a.load[sc.doff + (int64_t)n * T + t] * sc100;
+  x[T + t] = ren * sc100;
+  x[2 * T + t] = thr * sc100;
+  x[3 * T + t] = nl * sc100;
+  x[4 * T + t] = nren * sc100;
+  if (t == 0) {
+    float bcap = 0.f, gcap = 0.f;
+    const int f0 = a.term_ptr[nt.tptr_off + n], f1 = a.term_ptr[nt.tptr_off + n + 1];
+    for (int e = f0; e < f1; ++e) {
+      const int code = a.term[e];
+      if ((code & 3) == TT_BATT) bcap += a.eta[nt.eta_off + nt.G + nt.L + (code >> 2)];
+      if ((code & 3) == TT_GEN && a.gen_cost[nt.gen_off + (code >> 2)] > 0.f)
+        gcap += a.eta[nt.eta_off + (code >> 2)];
+    }
+    x[5 * T] = bcap * sc100;
+    x[5 * T + 1] = lcap * sc100;
+    x[5 * T + 2] = gcap * sc100;
+  }
+}
+
+__global__ void k_targets(Args a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, float* Y) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gid / T;
+  const int t = (int)(gid - row * T);
+  int b = -1;
+  for (int q = 0; q < nb; ++q) {
+    const int s = bscen[q];
+    const int r0 = rowoff[s];
+    if (row >= r0 && row < r0 + a.net[a.scen[s].net].N) {
+      b = q;
+      break;
+    }
+  }
+  if (b < 0) return;
+  const int s = bscen[b];
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int n = (int)(row - rowoff[s]);
+  const int64_t TT = T;
+  const double pi = a.yhat[sc.yoff + (int64_t)n * TT + t];
+  const float th = a.xhat[sc.xoff + (int64_t)(nt.G + nt.L) * TT + (int64_t)n * TT + t];
+  Y[row * 2 * T + t] = (float)asinh(pi / 100.0);
+  Y[row * 2 * T + T + t] = th * 0.1f;
+}
+
+// predicted node price and angle of (s, n, t)
+__device__ __forceinline__ double pred_price(const float* P, int64_t row, int T, int t) {
+  return 100.0 * sinh((double)P[row * 2 * T + t]);
+}
+__device__ __forceinline__ float pred_angle(const float* P, int64_t row, int T, int t) {
+  return 10.f * P[row * 2 * T + T + t];
+}
+
+// start point from a prediction, over the batch's variable tiles and row tiles
+template <int BS>
+__global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, const float* P) {
+  const bool rows = (int)blockIdx.x >= a.nvt;
+  const int tix = rows ? (int)blockIdx.x - a.nvt : (int)blockIdx.x;
+  const Tile tl = rows ? a.rtiles[tix] : a.vtiles[tix];
+  const int s = tl.scen;
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int T = sc.T;
+  const int64_t TT = T;
+  const int64_t r0 = rowoff[s];
+  float* xh = a.xhat + sc.xoff;
+  double* yh = a.yhat + sc.yoff;
+  const double r = a.r;
+  if (rows) {
+    if (tl.cls == RC_SOC) {
+      const int64_t base = (int64_t)(nt.N + nt.L) * TT + (int64_t)tl.start * TT;
+      for (int t = threadIdx.x; t < T; t += BS) yh[base + t] = 0.0;
+      return;
+    }
+    if ((int)threadIdx.x >= tl.count) return;
+    const int i = tl.start + threadIdx.x;
+    if (tl.cls == RC_BAL) {
+      const int n = i / T, t = i - n * T;
+      yh[i] = pred_price(P, r0 + n, T, t);
+    } else {  // flow dual from the line's stationarity at the clipped flow
+      const int l = i / T, t = i - l * T;
+      const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+      const float cap = a.eta[nt.eta_off + nt.G + l];
+      const float b = a.line_beta[nt.line_off + l];
+      const float f = clampf(b * (pred_angle(P, r0 + fr, T, t) - pred_angle(P, r0 + to, T, t)), -cap, cap);
+      yh[(int64_t)nt.N * TT + i] = r * f - (pred_price(P, r0 + to, T, t) - pred_price(P, r0 + fr, T, t));
+    }
+    return;
+  }
+  if ((int)threadIdx.x >= tl.count) return;
+  const int i = tl.start + threadIdx.x;
+  switch (tl.cls) {
+    case VC_GEN: {  // best response to the predicted price
+      const int g = i / T, t = i - g * T;
+      const int n = a.gen_node[nt.gen_off + g];
+      const double hi = (double)a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
+      const double p = (pred_price(P, r0 + n, T, t) - a.gen_cost[nt.gen_off + g]) / r;
+      xh[i] = (float)fmin(fmax(p, 0.0), hi);
+      break;
+    }
+    case VC_LINE: {
+      const int l = i / T, t = i - l * T;
+      const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+      const float cap = a.eta[nt.eta_off + nt.G + l];
+      const float b = a.line_beta[nt.line_off + l];
+      xh[(int64_t)nt.G * TT + i] =
+          clampf(b * (pred_angle(P, r0 + fr, T, t) - pred_angle(P, r0 + to, T, t)), -cap, cap);
+      break;
+    }
+    case VC_NODE: {
+      const int n = i / T, t = i - n * T;
+      xh[(int64_t)(nt.G + nt.L) * TT + i] = pred_angle(P, r0 + n, T, t);
+      // unserved load: best response, at most the node's load (a price
+      // just above the penalty would otherwise ask for (pi - lambda_u)/r)
+      const double u = (pred_price(P, r0 + n, T, t) - a.lambda_u) / r;
+      const double dmax = fmax((double)a.load[sc.doff + (int64_t)n * TT + t], 0.0);
+      xh[(int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i] = (float)fmin(fmax(u, 0.0), dmax);
+      break;
+    }
+    default: {
+      const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+      const int64_t BT = (int64_t)nt.B * TT;
+      xh[base + i] = 0.f;
+      xh[base + BT + i] = 0.f;
+      xh[base + 2 * BT + i] = 0.f;
+    }
+  }
+}
+
+hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
+                           int64_t rows, float* X, hipStream_t st) {
+  const int64_t n = rows * T;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, bscen, nb, rowoff, T, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
+                          int64_t rows, float* Y, hipStream_t st) {
+  const int64_t n = rows * T;
+  hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, bscen, nb, rowoff, T, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_start(const Args& a, int bs, const int32_t* rowoff, const float* P, hipStream_t st) {
+#define L_(B) hipLaunchKernelGGL(k_start<B>, dim3(a.nvt + a.nrt), dim3(B), 0, st, a, rowoff, P)
+  GP_DISPATCH_BS(bs, L_)
+#undef L_
   return hipGetLastError();
 }
 

@@ -1,0 +1,579 @@
+// Learned warm start: a small MLP (BF16 operands, FP32 accumulate) trained
+// and evaluated with hand-written MFMA GEMMs on gfx950.
+//
+// Layers: h_0 = x, h_{l+1} = relu(h_l W_l + b_l) for hidden layers, output
+// y = h_L W_L + b_L.  Weights live as FP32 masters (Adam state beside them)
+// and BF16 copies used by the GEMMs; activations are stored in BF16, the
+// pre-activation mask in the ReLU backward comes from the stored activation.
+//
+// GEMM: C[M x N] = op(A)[M x K] op(B)[K x N] with op = transpose or not,
+// row-major storage, zero-filled edges (no padding required).  Block tile
+// 128 x 128 x 32, 256 threads = 4 wavefronts of 64 x 64 (2 x 2 tiles of the
+// 32 x 32 x 16 BF16 MFMA).  Operand layout of v_mfma_f32_32x32x16_bf16: lane l
+// holds row (l mod 32) of A and column (l mod 32) of B for k in
+// [8 (l div 32), 8 (l div 32) + 8); accumulator register v of lane l is
+// C[8 (v div 4) + 4 (l div 32) + (v mod 4)][l mod 32].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/gridplan.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int LDA = BK + 8;  // LDS row pitch (bf16) to spread banks
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
+
+enum Epi { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2 };
+
+// C = op(A) op(B) (+ bias, relu).  A: TA ? [K x M] : [M x K]; B: TB ? [N x K] :
+// [K x N].  Outputs: Cf (FP32, nullable) and/or Cb (BF16, nullable), both
+// [M x N] row-major with leading dimension N.  accumulate: Cf += result.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, const __bf16* __restrict__ B,
+                                              float* __restrict__ Cf, __bf16* __restrict__ Cb,
+                                              const float* __restrict__ bias, int M, int N, int K, int epi,
+                                              int accumulate) {
+  __shared__ __bf16 As[BM * LDA];  // [m][k]
+  __shared__ __bf16 Bs[BN * LDA];  // [n][k]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // stage A tile: BM x BK elements, 16 per thread
+    for (int e = tid; e < BM * BK; e += 256) {
+      int mm, kk;
+      if (!TA) {
+        mm = e / BK;
+        kk = e % BK;
+      } else {
+        kk = e / BM;
+        mm = e % BM;
+      }
+      const int gm = m0 + mm, gk = k0 + kk;
+      __bf16 v = to_bf16(0.f);
+      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
+      As[mm * LDA + kk] = v;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      int nn, kk;
+      if (TB) {
+        nn = e / BK;
+        kk = e % BK;
+      } else {
+        kk = e / BN;
+        nn = e % BN;
+      }
+      const int gn = n0 + nn, gk = k0 + kk;
+      __bf16 v = to_bf16(0.f);
+      if (gn < N && gk < K) v = TB ? B[(int64_t)gn * K + gk] : B[(int64_t)gk * N + gn];
+      Bs[nn * LDA + kk] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      const int kq = ks + 8 * (lane >> 5);
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const __bf16* pa = &As[(wm + 32 * i + (lane & 31)) * LDA + kq];
+        const __bf16* pb = &Bs[(wn + 32 * i + (lane & 31)) * LDA + kq];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          af[i][q] = pa[q];
+          bfr[i][q] = pb[q];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = n0 + wn + 32 * j + (lane & 31);
+        if (row < M && col < N) {
+          float r = acc[i][j][v];
+          if (epi != EPI_NONE) r += bias[col];
+          if (epi == EPI_BIAS_RELU) r = fmaxf(r, 0.f);
+          const int64_t o = (int64_t)row * N + col;
+          if (Cf) Cf[o] = accumulate ? Cf[o] + r : r;
+          if (Cb) Cb[o] = to_bf16(r);
+        }
+      }
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// dY = (2 / count) (Y - T) per element, loss partials per block (FP64)
+__global__ void k_mse(const float* __restrict__ Y, const float* __restrict__ T, float* __restrict__ dY,
+                      __bf16* __restrict__ dYb, double* __restrict__ part, int64_t n, double scale) {
+  __shared__ double sh[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (i < n) {
+    const float d = Y[i] - T[i];
+    l = (double)d * d;
+    const float g = (float)(2.0 * scale) * d;
+    dY[i] = g;
+    dYb[i] = to_bf16(g);
+  }
+  sh[threadIdx.x] = l;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// ReLU backward through a stored BF16 activation: g *= (h > 0); BF16 copy
+__global__ void k_relu_bwd(float* __restrict__ g, const __bf16* __restrict__ h, __bf16* __restrict__ gb,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float v = ((float)h[i] > 0.f) ? g[i] : 0.f;
+    g[i] = v;
+    gb[i] = to_bf16(v);
+  }
+}
+
+// bias gradient: column sums of G [M x N] in a fixed order
+__global__ void k_colsum(const float* __restrict__ G, float* __restrict__ out, int M, int N) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  double s = 0.0;
+  for (int r = 0; r < M; ++r) s += G[(int64_t)r * N + c];
+  out[c] = (float)s;
+}
+
+// Adam on FP32 masters (bias-corrected), then the BF16 copy
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, __bf16* __restrict__ wb, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = to_bf16(wi);
+}
+
+struct MlpError {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void mfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw MlpError{code, buf};
+}
+
+#define MCHK(expr)                                                                       \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) mfail(GP_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+struct Buf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t c) {
+    if (c <= n && p) return;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    if (!c) return;
+    hipError_t e = hipMalloc((void**)&p, c * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      mfail(e == hipErrorOutOfMemory ? GP_ENOMEM : GP_EHIP, "hipMalloc failed");
+    }
+    n = c;
+  }
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+void launch_gemm(bool ta, bool tb, const __bf16* A, const __bf16* B, float* Cf, __bf16* Cb, const float* bias,
+                 int M, int N, int K, int epi, int accumulate, hipStream_t st) {
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
+  else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
+  MCHK(hipGetLastError());
+}
+
+int nblk(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+struct gp_mlp {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<int> dims;  // n_in, width..., n_out
+  int L = 0;              // number of linear layers
+  std::vector<int64_t> woff, boff;  // offsets into the flat parameter vector
+  int64_t nparam = 0;
+  Buf<float> w, g, m, v;  // FP32 masters, gradients, Adam moments
+  Buf<__bf16> wb;         // BF16 copy (weights only; biases stay FP32)
+  int64_t step = 0;
+  // activations for a batch
+  int64_t cap_rows = 0;
+  std::vector<Buf<__bf16>> act;  // act[l]: input of layer l, [rows x dims[l]] BF16
+  Buf<float> out, dy;            // [rows x n_out] FP32
+  Buf<float> gf;                 // FP32 gradient wrt a hidden activation (largest width)
+  Buf<__bf16> gb0, gb1;          // BF16 gradients (ping-pong)
+  Buf<double> part;
+  ~gp_mlp() {
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace {
+
+thread_local std::string g_mlp_init_error;
+
+void ensure_rows(gp_mlp* m, int64_t rows) {
+  if (rows <= m->cap_rows) return;
+  m->act.resize(m->L);
+  for (int l = 0; l < m->L; ++l) m->act[l].alloc((size_t)rows * m->dims[l]);
+  const int nout = m->dims.back();
+  m->out.alloc((size_t)rows * nout);
+  m->dy.alloc((size_t)rows * nout);
+  int wmax = 0;
+  for (int d : m->dims) wmax = std::max(wmax, d);
+  m->gf.alloc((size_t)rows * wmax);
+  m->gb0.alloc((size_t)rows * wmax);
+  m->gb1.alloc((size_t)rows * wmax);
+  m->part.alloc((size_t)nblk(rows * (int64_t)nout) + 1);
+  m->cap_rows = rows;
+}
+
+// forward over `rows` rows whose BF16 input is already in act[0]
+void forward(gp_mlp* m, int64_t rows) {
+  hipStream_t st = m->stream;
+  for (int l = 0; l < m->L; ++l) {
+    const int K = m->dims[l], N = m->dims[l + 1];
+    const __bf16* W = m->wb.p + m->woff[l];
+    const float* b = m->w.p + m->boff[l];
+    if (l + 1 < m->L)
+      launch_gemm(false, false, m->act[l].p, W, nullptr, m->act[l + 1].p, b, (int)rows, N, K, EPI_BIAS_RELU, 0, st);
+    else
+      launch_gemm(false, false, m->act[l].p, W, m->out.p, nullptr, b, (int)rows, N, K, EPI_BIAS, 0, st);
+  }
+}
+
+void load_input(gp_mlp* m, const float* X, int64_t rows, int on_device) {
+  const int64_t n = rows * m->dims[0];
+  Buf<float> tmp;
+  const float* src = X;
+  if (!on_device) {
+    tmp.alloc(n);
+    MCHK(hipMemcpyAsync(tmp.p, X, n * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    src = tmp.p;
+  }
+  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(n)), dim3(256), 0, m->stream, src, m->act[0].p, n);
+  MCHK(hipGetLastError());
+  if (!on_device) MCHK(hipStreamSynchronize(m->stream));
+}
+
+// mean squared error over rows x n_out and the parameter gradient in m->g
+double loss_backward(gp_mlp* m, const float* Tgt, int64_t rows, int on_device) {
+  hipStream_t st = m->stream;
+  const int nout = m->dims.back();
+  const int64_t n = rows * nout;
+  Buf<float> tmp;
+  const float* t = Tgt;
+  if (!on_device) {
+    tmp.alloc(n);
+    MCHK(hipMemcpyAsync(tmp.p, Tgt, n * sizeof(float), hipMemcpyHostToDevice, st));
+    t = tmp.p;
+  }
+  const int nb = nblk(n);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, m->out.p, t, m->dy.p, m->gb0.p, m->part.p, n,
+                     1.0 / (double)n);
+  MCHK(hipGetLastError());
+  // layer L-1 .. 0
+  float* gcur_f = m->dy.p;
+  __bf16* gcur_b = m->gb0.p;
+  __bf16* gnext_b = m->gb1.p;
+  for (int l = m->L - 1; l >= 0; --l) {
+    const int K = m->dims[l], N = m->dims[l + 1];
+    // dW_l = act_l^T g  [K x N]
+    launch_gemm(true, false, m->act[l].p, gcur_b, m->g.p + m->woff[l], nullptr, nullptr, K, N, (int)rows, EPI_NONE,
+                0, st);
+    hipLaunchKernelGGL(k_colsum, dim3(nblk(N)), dim3(256), 0, st, gcur_f, m->g.p + m->boff[l], (int)rows, N);
+    MCHK(hipGetLastError());
+    if (l > 0) {
+      // g_prev = g W_l^T, then through the ReLU of layer l-1's output (act_l)
+      launch_gemm(false, true, gcur_b, m->wb.p + m->woff[l], m->gf.p, nullptr, nullptr, (int)rows, K, N, EPI_NONE,
+                  0, st);
+      const int64_t nk = rows * K;
+      hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(nk)), dim3(256), 0, st, m->gf.p, m->act[l].p, gnext_b, nk);
+      MCHK(hipGetLastError());
+      gcur_f = m->gf.p;
+      std::swap(gcur_b, gnext_b);
+    }
+  }
+  std::vector<double> hp(nb);
+  MCHK(hipMemcpyAsync(hp.data(), m->part.p, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  MCHK(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (double v : hp) s += v;
+  return s / (double)n;
+}
+
+void check_dims(const gp_mlp* m, int64_t rows) {
+  if (rows < 1 || rows > (int64_t)1 << 30) mfail(GP_EINVAL, "rows must be in [1, 2^30]");
+  (void)m;
+}
+
+int mguard(gp_mlp* m, const std::function<int()>& f) {
+  try {
+    const int rc = f();
+    if (m) m->err.clear();
+    return rc;
+  } catch (const MlpError& e) {
+    if (m) m->err = e.msg;
+    return e.code;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int mlp_init(gp_mlp** out, int32_t n_in, int32_t width, int32_t hidden_layers, int32_t n_out, uint64_t seed,
+             void* hip_stream) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  gp_mlp* m = nullptr;
+  try {
+    if (n_in < 1 || width < 1 || hidden_layers < 0 || n_out < 1 || n_in > 65536 || width > 65536 || n_out > 65536)
+      mfail(GP_EINVAL, "bad layer sizes");
+    m = new gp_mlp();
+    if (hip_stream) {
+      m->stream = (hipStream_t)hip_stream;
+    } else {
+      MCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
+      m->own_stream = true;
+    }
+    m->dims.push_back(n_in);
+    for (int l = 0; l < hidden_layers; ++l) m->dims.push_back(width);
+    m->dims.push_back(n_out);
+    m->L = (int)m->dims.size() - 1;
+    int64_t o = 0;
+    for (int l = 0; l < m->L; ++l) {
+      m->woff.push_back(o);
+      o += (int64_t)m->dims[l] * m->dims[l + 1];
+    }
+    for (int l = 0; l < m->L; ++l) {
+      m->boff.push_back(o);
+      o += m->dims[l + 1];
+    }
+    m->nparam = o;
+    // He-uniform weights, zero biases (seeded, host side)
+    std::vector<float> w(o, 0.f);
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < m->L; ++l) {
+      const float a = std::sqrt(6.0f / (float)m->dims[l]);
+      std::uniform_real_distribution<float> U(-a, a);
+      for (int64_t i = 0; i < (int64_t)m->dims[l] * m->dims[l + 1]; ++i) w[m->woff[l] + i] = U(rng);
+    }
+    m->w.alloc(o);
+    m->g.alloc(o);
+    m->m.alloc(o);
+    m->v.alloc(o);
+    m->wb.alloc(o);
+    MCHK(hipMemcpyAsync(m->w.p, w.data(), o * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemsetAsync(m->m.p, 0, o * sizeof(float), m->stream));
+    MCHK(hipMemsetAsync(m->v.p, 0, o * sizeof(float), m->stream));
+    MCHK(hipMemsetAsync(m->g.p, 0, o * sizeof(float), m->stream));
+    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(o)), dim3(256), 0, m->stream, m->w.p, m->wb.p, o);
+    MCHK(hipGetLastError());
+    MCHK(hipStreamSynchronize(m->stream));
+  } catch (const MlpError& e) {
+    g_mlp_init_error = e.msg;
+    delete m;
+    return e.code;
+  }
+  *out = m;
+  return GP_OK;
+}
+
+int mlp_num_params(const gp_mlp* m, int64_t* n) {
+  if (!m || !n) return GP_EINVAL;
+  *n = m->nparam;
+  return GP_OK;
+}
+
+int mlp_get_params(gp_mlp* m, float* w_out) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!w_out) mfail(GP_EINVAL, "w_out is NULL");
+    MCHK(hipMemcpyAsync(w_out, m->w.p, m->nparam * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+int mlp_set_params(gp_mlp* m, const float* w_in) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!w_in) mfail(GP_EINVAL, "w_in is NULL");
+    for (int64_t i = 0; i < m->nparam; ++i)
+      if (!std::isfinite(w_in[i])) mfail(GP_EINVAL, "parameter %lld is not finite", (long long)i);
+    MCHK(hipMemcpyAsync(m->w.p, w_in, m->nparam * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(m->nparam)), dim3(256), 0, m->stream, m->w.p, m->wb.p, m->nparam);
+    MCHK(hipGetLastError());
+    MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+int mlp_forward(gp_mlp* m, const float* X, int64_t rows, int32_t on_device, float* Y) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!X || !Y) mfail(GP_EINVAL, "X and Y must not be NULL");
+    check_dims(m, rows);
+    ensure_rows(m, rows);
+    load_input(m, X, rows, on_device);
+    forward(m, rows);
+    const int64_t n = rows * m->dims.back();
+    MCHK(hipMemcpyAsync(Y, m->out.p, n * sizeof(float), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+int mlp_loss_grad(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device, double* loss,
+                  float* grad_out) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!X || !T) mfail(GP_EINVAL, "X and T must not be NULL");
+    check_dims(m, rows);
+    ensure_rows(m, rows);
+    load_input(m, X, rows, on_device);
+    forward(m, rows);
+    const double l = loss_backward(m, T, rows, on_device);
+    if (loss) *loss = l;
+    if (grad_out) {
+      MCHK(hipMemcpyAsync(grad_out, m->g.p, m->nparam * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+      MCHK(hipStreamSynchronize(m->stream));
+    }
+    return GP_OK;
+  });
+}
+
+int mlp_adam_step(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device, double lr,
+                  double* loss) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!X || !T) mfail(GP_EINVAL, "X and T must not be NULL");
+    if (!(lr > 0) || !std::isfinite(lr)) mfail(GP_EINVAL, "lr must be > 0");
+    check_dims(m, rows);
+    ensure_rows(m, rows);
+    load_input(m, X, rows, on_device);
+    forward(m, rows);
+    const double l = loss_backward(m, T, rows, on_device);
+    if (loss) *loss = l;
+    m->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
+    // weights (with their BF16 copies) then biases
+    const int64_t nw = m->boff[0];
+    hipLaunchKernelGGL(k_adam, dim3(nblk(nw)), dim3(256), 0, m->stream, m->w.p, m->g.p, m->m.p, m->v.p, m->wb.p, nw,
+                       (float)lr, b1, b2, 1e-8f, c1, c2);
+    const int64_t nbias = m->nparam - nw;
+    hipLaunchKernelGGL(k_adam, dim3(nblk(nbias)), dim3(256), 0, m->stream, m->w.p + nw, m->g.p + nw, m->m.p + nw,
+                       m->v.p + nw, (__bf16*)nullptr, nbias, (float)lr, b1, b2, 1e-8f, c1, c2);
+    MCHK(hipGetLastError());
+    MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+// plain GEMM through the same kernel (for tests): C = op(A) op(B), BF16 in
+// (host FP32 rounded to BF16), FP32 out.  Host pointers.
+int mlp_gemm_test(const float* A, const float* B, float* C, int32_t M, int32_t N, int32_t K, int32_t ta,
+                  int32_t tb) {
+  try {
+    if (!A || !B || !C || M < 1 || N < 1 || K < 1) return GP_EINVAL;
+    hipStream_t st = nullptr;
+    Buf<float> fa, fb, fc;
+    Buf<__bf16> ba, bb;
+    const int64_t na = (int64_t)M * K, nb = (int64_t)K * N, nc = (int64_t)M * N;
+    fa.alloc(na);
+    fb.alloc(nb);
+    fc.alloc(nc);
+    ba.alloc(na);
+    bb.alloc(nb);
+    MCHK(hipMemcpy(fa.p, A, na * sizeof(float), hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(fb.p, B, nb * sizeof(float), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(na)), dim3(256), 0, st, fa.p, ba.p, na);
+    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(nb)), dim3(256), 0, st, fb.p, bb.p, nb);
+    launch_gemm(ta != 0, tb != 0, ba.p, bb.p, fc.p, nullptr, nullptr, M, N, K, EPI_NONE, 0, st);
+    MCHK(hipMemcpy(C, fc.p, nc * sizeof(float), hipMemcpyDeviceToHost));
+    return GP_OK;
+  } catch (const MlpError& e) {
+    g_mlp_init_error = e.msg;
+    return e.code;
+  }
+}
+
+void mlp_free(gp_mlp* m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  delete m;
+}
+
+const char* mlp_last_error(const gp_mlp* m) { return m ? m->err.c_str() : g_mlp_init_error.c_str(); }
+
+}  // extern "C"

@@ -24,10 +24,15 @@ hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipSt
 hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed,
                          int variant, int qblocks, unsigned long long* qc, unsigned int* qd);
 hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st);
-hipError_t launch_reset(const Args& a, int bs, int cold, hipStream_t st);
+hipError_t launch_reset(const Args& a, int bs, int mode, hipStream_t st);
 hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st);
 hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj,
                        hipStream_t st);
+hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
+                           int64_t rows, float* X, hipStream_t st);
+hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
+                          int64_t rows, float* Y, hipStream_t st);
+hipError_t launch_start(const Args& a, int bs, const int32_t* rowoff, const float* P, hipStream_t st);
 }  // namespace gp
 
 using namespace gp;
@@ -191,6 +196,7 @@ struct gp_plan {
   PinBuf<double> h_stats;
   DevBuf<double> d_gpart;
   DevBuf<int64_t> d_goff;
+  DevBuf<int32_t> d_rowoff;  // learned warm start: first row of each scenario
   PinBuf<double> h_gpart;
   int64_t gpart_n = 0;
   // sweep launch configuration (tuned per batch unless fixed by options)
@@ -209,6 +215,7 @@ struct gp_plan {
   // solution bookkeeping
   std::vector<int> has_solution;
   std::vector<float> last_cw, last_cwf;
+  std::vector<int> cold_iters;  // per network: iterations of its last converged cold solve (0 = none yet)
   std::vector<int> solved_batch;
   std::vector<float> eta_f;  // capacities of the last solve
   std::vector<double> eta_last;
@@ -533,6 +540,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->has_solution.assign(p->S, 0);
   p->last_cw.assign(p->S, 0.f);
   p->last_cwf.assign(p->S, 1.f);
+  p->cold_iters.assign(p->nets.size(), 0);
   for (int q = 0; q < p->S; ++q) p->h_cwf[q] = 1.f;
   HIPCHK(hipStreamSynchronize(st));
 }
@@ -833,6 +841,10 @@ Kkt kkt_of(const gp_plan* p, const double* st, double einf, double e2 = 0.0, dou
 
 // The restarted Halpern loop shared by the dispatch solve (mode 0) and the
 // adjoint solve (mode 1).  Returns the number of unconverged entries.
+// a warm start is screened out when its KKT residual exceeds this multiple
+// of the cold start's
+constexpr double kWarmScreen = 100.0;
+
 int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
             std::vector<gp_solve_stats>& out, double omega) {
   const std::vector<int>& batch = p->batch;
@@ -843,26 +855,6 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   const int max_iter = p->opt.max_iter > 0 ? p->opt.max_iter : 400000;
   const double tol = p->opt.tol > 0 ? p->opt.tol : 1e-4;
   const float c0 = (float)(p->opt.rho0 > 0 ? p->opt.rho0 : 10.0);
-  std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
-  std::fill(p->h_active.p, p->h_active.p + p->S, 0);
-  std::fill(p->h_kbase.p, p->h_kbase.p + p->S, 0);
-  for (int b = 0; b < nb; ++b) {
-    const int s = batch[b];
-    p->h_restart[s] = 1;
-    p->h_active[s] = 1;
-    const bool w = warm && p->last_cw[s] > 0.f;
-    p->h_cw[s] = w ? p->last_cw[s] : c0;
-    p->h_cwf[s] = w ? p->last_cwf[s] : 1.f;
-  }
-  upload_control(p);
-  // start point: zeros (cold) or the stored (xhat, yhat) (warm)
-  HIPCHK(launch_reset(a, block_size(p), warm ? 0 : 1, p->stream));
-  // the control uploads read pinned host memory asynchronously: wait before
-  // the host rewrites it
-  HIPCHK(hipStreamSynchronize(p->stream));
-  std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
-  upload_control(p);
-  run_check_only(p, a);
   std::vector<double> e2(nb, 0.0), q2(nb, 1.0);
   for (int b = 0; b < nb; ++b) {
     if (mode == 0) {
@@ -873,8 +865,67 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   const Tune& tn = p->tune;
   auto stop_of = [&](const Kkt& k) { return tn.stop_norm == 2 ? k.kkt2 : k.kkt; };
   auto rmet_of = [&](const Kkt& k) { return tn.rmetric == 1 ? k.kkt2 : k.kkt; };
+  const int bs = block_size(p);
+  // per scenario: warm when asked for and a stored point exists
+  std::vector<int32_t> start(nb, 0);
+  std::fill(p->h_active.p, p->h_active.p + p->S, 0);
+  std::fill(p->h_kbase.p, p->h_kbase.p + p->S, 0);
+  int n_warm = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int s = batch[b];
+    p->h_active[s] = 1;
+    start[b] = (warm && (mode != 0 || p->has_solution[s])) ? 1 : 0;
+    n_warm += start[b];
+    const bool w = start[b] && p->last_cw[s] > 0.f;
+    p->h_cw[s] = w ? p->last_cw[s] : c0;
+    p->h_cwf[s] = w ? p->last_cwf[s] : 1.f;
+  }
+  // reset the batch scenarios selected by `pick` (the control uploads read
+  // pinned host memory asynchronously: wait before the host rewrites it)
+  auto reset_where = [&](int how, const std::function<bool(int)>& pick) {
+    std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+    for (int b = 0; b < nb; ++b) p->h_restart[batch[b]] = pick(b) ? 1 : 0;
+    upload_control(p);
+    HIPCHK(launch_reset(a, bs, how, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  };
+  if (n_warm < nb) reset_where(RESET_COLD, [&](int b) { return start[b] == 0; });
+  if (n_warm > 0) reset_where(RESET_WARM, [&](int b) { return start[b] == 1; });
+  if (n_warm > 0 && !p->opt.accept_warm) {
+    // Screen each warm start against the cold start: the residual at the
+    // warm point, then at zero (probe), then the warm point is put back and
+    // the scenarios whose warm residual exceeds kWarmScreen times the cold
+    // one go back to zeros (a NaN residual counts as worse).  The residual
+    // of a start does not rank starts by the work left (a point with exact
+    // prices but bang-bang generator outputs measures ~10-50 against ~1 at
+    // zero and still needs a fraction of the cold iterations), so the screen
+    // only removes predictions that are far off; the stall rule below
+    // bounds what an accepted start can cost.
+    run_check_only(p, a);
+    std::vector<double> kw(nb), kc(nb);
+    for (int b = 0; b < nb; ++b) kw[b] = stop_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+    reset_where(RESET_PROBE, [&](int b) { return start[b] == 1; });
+    run_check_only(p, a);
+    for (int b = 0; b < nb; ++b) kc[b] = stop_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+    reset_where(RESET_RESTORE, [&](int b) { return start[b] == 1; });
+    bool any = false;
+    for (int b = 0; b < nb; ++b) {
+      if (p->opt.verbose && start[b] == 1)
+        fprintf(stderr, "[gridplan] warm start of scenario %d: KKT %.3e, cold %.3e%s\n", batch[b], kw[b], kc[b],
+                kw[b] <= kWarmScreen * kc[b] ? "" : " (rejected)");
+      if (start[b] != 1 || kw[b] <= kWarmScreen * kc[b]) continue;
+      p->h_cw[batch[b]] = c0;
+      p->h_cwf[batch[b]] = 1.f;
+      start[b] = 2;
+      any = true;
+    }
+    if (any) reset_where(RESET_COLD, [&](int b) { return start[b] == 2; });
+  }
+  std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+  upload_control(p);
+  run_check_only(p, a);
   std::vector<double> k_restart(nb), k_last(nb, HUGE_VAL);
-  std::vector<int> inner(nb, 0), total(nb, 0), nrest(nb, 0), done(nb, 0);
+  std::vector<int> inner(nb, 0), total(nb, 0), nrest(nb, 0), done(nb, 0), go_cold(nb, 0), since_cold(nb, 0);
   out.assign(nb, gp_solve_stats{});
   for (int b = 0; b < nb; ++b) {
     const Kkt k = kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]);
@@ -906,6 +957,7 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       const Kkt k = kkt_of(p, st, einf[b], e2[b], q2[b]);
       total[b] += ce;
       inner[b] += ce;
+      since_cold[b] += ce;
       out[b].r_pri = k.r_pri;
       out[b].r_dual = k.r_dual;
       out[b].r_gap = k.r_gap;
@@ -913,13 +965,19 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       out[b].cost = st[ST_P];
       out[b].emis = st[ST_EMIS];
       out[b].iters = total[b];
-      if (!std::isfinite(k.kkt)) {
-        // numerical breakdown: restart cold with the initial weight
-        p->h_restart[s] = 1;
+      const int pct = p->opt.stall_pct > 0 ? p->opt.stall_pct : 100;
+      const int ref = mode == 0 ? (int)std::min<int64_t>((int64_t)p->cold_iters[p->scen[s].net] * pct / 100, INT32_MAX) : 0;
+      const bool stalled = start[b] == 1 && !p->opt.accept_warm && ref > 0 && total[b] >= ref && stop_of(k) > tol;
+      if (!std::isfinite(k.kkt) || stalled) {
+        // numerical breakdown, or a warm start that has used the iterations
+        // of a cold solve of this network: start cold with the initial weight
+        go_cold[b] = 1;
         p->h_cw[s] = c0;
         p->h_cwf[s] = 1.f;
-        any_restart = true;
+        if (stalled) start[b] = 3;
+        since_cold[b] = 0;
         inner[b] = 0;
+        p->h_kbase[s] = 0;
         k_restart[b] = HUGE_VAL;
         k_last[b] = HUGE_VAL;
         continue;
@@ -932,7 +990,7 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       }
       const double m = rmet_of(k);
       const bool go = m <= tn.bsuff * k_restart[b] || (m <= tn.bnec * k_restart[b] && m > k_last[b]) ||
-                      inner[b] >= tn.art * total[b];
+                      inner[b] >= tn.art * since_cold[b];
       if (p->trace && b == 0)
         fprintf(stderr, "[trace] mode %d it %d kkt %.3e bal %.2e flow %.2e soc %.2e dual %.2e gap %.2e c %.4g cf %.4g dx %.4g dy %.4g restart %d\n",
                 mode, total[b], k.kkt, k.r_bal, k.r_flow, k.r_soc, k.r_dual, k.r_gap, (double)p->h_cw[s],
@@ -969,9 +1027,20 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
     }
     if (any_restart) {
       upload_control(p);
-      HIPCHK(launch_reset(a, block_size(p), 0, p->stream));
+      HIPCHK(launch_reset(a, bs, RESET_WARM, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));  // before the pinned flags are cleared
       std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+    }
+    if (std::find(go_cold.begin(), go_cold.end(), 1) != go_cold.end()) {
+      // from here on the scenario runs exactly as a cold start: zeros, the
+      // initial weights, and the restart reference measured at zero
+      reset_where(RESET_COLD, [&](int b) { return go_cold[b] == 1; });
+      std::fill(p->h_restart.p, p->h_restart.p + p->S, 0);
+      upload_control(p);
+      run_check_only(p, a);
+      for (int b = 0; b < nb; ++b)
+        if (go_cold[b]) k_restart[b] = rmet_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+      std::fill(go_cold.begin(), go_cold.end(), 0);
     }
     if (p->opt.verbose && (it / ce) % 16 == 0) {
       double worst = 0;
@@ -983,11 +1052,24 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   for (int b = 0; b < nb; ++b) {
     out[b].restarts = nrest[b];
     out[b].status = done[b] ? 0 : 1;
+    out[b].start = start[b];
     out[b].primal_weight = p->h_cw[batch[b]];
     if (mode == 0) {
       p->last_cw[batch[b]] = p->h_cw[batch[b]];
       p->last_cwf[batch[b]] = p->h_cwf[batch[b]];
     }
+  }
+  // converged solves from zeros set their network's reference for the stall
+  // rule (the largest count of this call)
+  if (mode == 0) {
+    std::vector<int> ref(p->cold_iters.size(), 0);
+    for (int b = 0; b < nb; ++b)
+      if (done[b] && start[b] != 1 && since_cold[b] > 0) {
+        int& r = ref[p->scen[batch[b]].net];
+        r = std::max(r, since_cold[b]);
+      }
+    for (size_t n = 0; n < ref.size(); ++n)
+      if (ref[n] > 0) p->cold_iters[n] = ref[n];
   }
   return remaining;
 }
@@ -1030,14 +1112,11 @@ int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, i
   HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
   build_tiles(p, batch);
   autotune(p, batch);
-  bool all_warm = warm == 1;
-  for (int s : batch) all_warm = all_warm && p->has_solution[s];
   std::vector<double> einf;
   for (int s : batch) einf.push_back(p->scen[s].einf);
   std::vector<gp_solve_stats> st;
-  // a warm start needs a stored solution for every listed scenario; mixed
-  // batches start cold
-  const int rem = iterate(p, 0, einf, all_warm ? 1 : 0, st, 0.0);
+  // scenarios without a stored point start cold
+  const int rem = iterate(p, 0, einf, warm, st, 0.0);
   for (int b = 0; b < nb; ++b) {
     p->has_solution[batch[b]] = 1;
     if (cost_out) cost_out[b] = st[b].cost;
@@ -1156,8 +1235,10 @@ int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void
   try {
     validate_case(cs);
     if (opt) {
-      if (opt->tol < 0 || opt->max_iter < 0 || opt->check_every < 0 || opt->rho0 < 0)
+      if (opt->tol < 0 || opt->max_iter < 0 || opt->check_every < 0 || opt->rho0 < 0 || opt->stall_pct < 0)
         fail(GP_EINVAL, "negative option");
+      if (!std::isfinite(opt->tol) || !std::isfinite(opt->rho0)) fail(GP_EINVAL, "options must be finite");
+      if (opt->accept_warm != 0 && opt->accept_warm != 1) fail(GP_EINVAL, "accept_warm must be 0 or 1");
       if (opt->block != 0 && opt->block != 64 && opt->block != 128 && opt->block != 256 && opt->block != 512)
         fail(GP_EINVAL, "block must be 0, 64, 128, 256 or 512");
       if (opt->variant < 0 || opt->variant > 2) fail(GP_EINVAL, "variant must be 0, 1 or 2");
@@ -1318,6 +1399,100 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
     for (auto& e : ev) (void)hipEventDestroy(e);
     *ms_dual = t1 / iters;
     *ms_primal = t2 / iters;
+    return GP_OK;
+  });
+}
+
+// rows of the learned warm start: one per (listed scenario, node)
+static int64_t nn_layout(gp_plan* p, const std::vector<int>& batch, std::vector<int32_t>& rowoff, int& T) {
+  rowoff.assign(p->S, -1);
+  int64_t rows = 0;
+  T = p->scen[batch[0]].T;
+  for (int s : batch) {
+    if (p->scen[s].T != T) fail(GP_EINVAL, "all listed scenarios must share the horizon T");
+    rowoff[s] = (int32_t)rows;
+    rows += p->nets[p->scen[s].net].N;
+  }
+  return rows;
+}
+
+int plan_nn_rows(gp_plan* p, const int32_t* scen, int32_t nb, int64_t* rows, int32_t* T) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    std::vector<int> batch;
+    check_batch(p, scen, nb, batch);
+    std::vector<int32_t> ro;
+    int t = 0;
+    const int64_t r = nn_layout(p, batch, ro, t);
+    if (rows) *rows = r;
+    if (T) *T = t;
+    return GP_OK;
+  });
+}
+
+static void nn_prepare(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, std::vector<int>& batch,
+                       int64_t& rows, int& T) {
+  check_batch(p, scen, nb, batch);
+  std::vector<int32_t> ro;
+  rows = nn_layout(p, batch, ro, T);
+  if (eta) {
+    check_eta(p, eta);
+    std::vector<float> ef(std::max<int64_t>(p->K, 1));
+    for (int64_t j = 0; j < p->K; ++j) ef[j] = (float)eta[j];
+    HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+  }
+  build_tiles(p, batch);
+  p->d_rowoff.upload(ro, p->stream);
+  HIPCHK(hipStreamSynchronize(p->stream));
+}
+
+int plan_features(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, float* X_dev) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (!X_dev || !eta) fail(GP_EINVAL, "eta and X must not be NULL");
+    std::vector<int> batch;
+    int64_t rows;
+    int T;
+    nn_prepare(p, eta, scen, nb, batch, rows, T);
+    HIPCHK(launch_features(make_args(p, 0), p->d_bscen.p, nb, p->d_rowoff.p, T, rows, X_dev, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return GP_OK;
+  });
+}
+
+int plan_targets(gp_plan* p, const int32_t* scen, int32_t nb, float* Y_dev) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (!Y_dev) fail(GP_EINVAL, "Y must not be NULL");
+    std::vector<int> batch;
+    int64_t rows;
+    int T;
+    nn_prepare(p, nullptr, scen, nb, batch, rows, T);
+    for (int s : batch)
+      if (!p->has_solution[s]) fail(GP_ESTATE, "scenario %d has no solution", s);
+    HIPCHK(launch_targets(make_args(p, 0), p->d_bscen.p, nb, p->d_rowoff.p, T, rows, Y_dev, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return GP_OK;
+  });
+}
+
+int plan_start_from_prediction(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb,
+                               const float* P_dev) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (!P_dev || !eta) fail(GP_EINVAL, "eta and P must not be NULL");
+    std::vector<int> batch;
+    int64_t rows;
+    int T;
+    nn_prepare(p, eta, scen, nb, batch, rows, T);
+    HIPCHK(launch_start(make_args(p, 0), block_size(p), p->d_rowoff.p, P_dev, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (int s : batch) {
+      p->has_solution[s] = 1;
+      p->last_cw[s] = 0.f;  // a predicted start begins with the initial weights
+      p->last_cwf[s] = 1.f;
+    }
     return GP_OK;
   });
 }

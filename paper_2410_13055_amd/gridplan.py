@@ -21,6 +21,9 @@ GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ESTATE = -1, -2, -3, -4
 
 EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "plan_step",
            "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_tuning",
+           "plan_nn_rows", "plan_features", "plan_targets", "plan_start_from_prediction",
+           "mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
+           "mlp_loss_grad", "mlp_adam_step", "mlp_gemm_test", "mlp_free", "mlp_last_error",
            "plan_sizes", "plan_free", "plan_last_error")
 
 
@@ -59,17 +62,18 @@ class gp_case_desc(C.Structure):
 class gp_options(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("block", C.c_int32), ("no_graph", C.c_int32), ("rho0", C.c_double),
-                ("verbose", C.c_int32), ("variant", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("verbose", C.c_int32), ("variant", C.c_int32), ("accept_warm", C.c_int32),
+                ("stall_pct", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class gp_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
-                ("pad", C.c_int32), ("r_pri", C.c_double), ("r_dual", C.c_double),
+                ("start", C.c_int32), ("r_pri", C.c_double), ("r_dual", C.c_double),
                 ("r_gap", C.c_double), ("kkt", C.c_double), ("cost", C.c_double),
                 ("emis", C.c_double), ("primal_weight", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -105,6 +109,32 @@ def load(path: str = LIB_PATH):
     lib.plan_time_sweeps.restype = C.c_int
     lib.plan_tuning.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_double)]
     lib.plan_tuning.restype = C.c_int
+    lib.plan_nn_rows.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, P(C.c_int64), P(C.c_int32)]
+    lib.plan_features.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32, C.c_void_p]
+    lib.plan_targets.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_void_p]
+    lib.plan_start_from_prediction.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32,
+                                               C.c_void_p]
+    for f in ("plan_nn_rows", "plan_features", "plan_targets", "plan_start_from_prediction"):
+        getattr(lib, f).restype = C.c_int
+    lib.mlp_init.argtypes = [P(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                             C.c_void_p]
+    lib.mlp_num_params.argtypes = [C.c_void_p, P(C.c_int64)]
+    lib.mlp_get_params.argtypes = [C.c_void_p, P(C.c_float)]
+    lib.mlp_set_params.argtypes = [C.c_void_p, P(C.c_float)]
+    lib.mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                  P(C.c_double), P(C.c_float)]
+    lib.mlp_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
+                                  P(C.c_double)]
+    lib.mlp_gemm_test.argtypes = [P(C.c_float), P(C.c_float), P(C.c_float), C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int32, C.c_int32]
+    for f in ("mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
+              "mlp_loss_grad", "mlp_adam_step", "mlp_gemm_test"):
+        getattr(lib, f).restype = C.c_int
+    lib.mlp_free.argtypes = [C.c_void_p]
+    lib.mlp_free.restype = None
+    lib.mlp_last_error.argtypes = [C.c_void_p]
+    lib.mlp_last_error.restype = C.c_char_p
     lib.plan_sizes.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32)]
     lib.plan_sizes.restype = C.c_int
     lib.plan_free.argtypes = [C.c_void_p]
@@ -159,9 +189,9 @@ class _Descriptor:
 
 
 def options(tol=1e-4, max_iter=0, check_every=0, block=0, no_graph=0, rho0=0.0, verbose=0,
-            variant=0):
+            variant=0, accept_warm=0, stall_pct=0):
     return gp_options(float(tol), int(max_iter), int(check_every), int(block), int(no_graph),
-                      float(rho0), int(verbose), int(variant))
+                      float(rho0), int(verbose), int(variant), int(accept_warm), int(stall_pct))
 
 
 def current_stream():
@@ -284,8 +314,138 @@ class Plan:
         self.lib.plan_tuning(self.h, C.byref(b), C.byref(v), C.byref(c), _ptr(tab, C.c_double))
         return int(b.value), int(v.value), int(c.value), tab.reshape(2, 3)
 
+    # ---- learned warm start (device matrices are torch CUDA tensors) ----
+    def nn_rows(self, scen):
+        idx = self._idx(scen)
+        r, t = C.c_int64(), C.c_int32()
+        self._check(self.lib.plan_nn_rows(self.h, _ptr(idx, C.c_int32), idx.shape[0], C.byref(r), C.byref(t)),
+                    allow_nc=False)
+        return int(r.value), int(t.value)
+
+    def features(self, eta, scen, X):
+        """Fill the float32 CUDA tensor X [rows, 5T+3] with node features."""
+        e = np.ascontiguousarray(eta, np.float64)
+        idx = self._idx(scen)
+        _check_dev(X)
+        self._check(self.lib.plan_features(self.h, _ptr(e, C.c_double), _ptr(idx, C.c_int32), idx.shape[0],
+                                           C.c_void_p(X.data_ptr())), allow_nc=False)
+
+    def targets(self, scen, Y):
+        """Fill the float32 CUDA tensor Y [rows, 2T] from the stored solutions."""
+        idx = self._idx(scen)
+        _check_dev(Y)
+        self._check(self.lib.plan_targets(self.h, _ptr(idx, C.c_int32), idx.shape[0], C.c_void_p(Y.data_ptr())),
+                    allow_nc=False)
+
+    def start_from_prediction(self, eta, scen, P):
+        """Seed the next warm solve of the scenarios from a prediction tensor."""
+        e = np.ascontiguousarray(eta, np.float64)
+        idx = self._idx(scen)
+        _check_dev(P)
+        self._check(self.lib.plan_start_from_prediction(self.h, _ptr(e, C.c_double), _ptr(idx, C.c_int32),
+                                                        idx.shape[0], C.c_void_p(P.data_ptr())), allow_nc=False)
+
     def set_start(self, s: int, x, y=None):
         x = np.ascontiguousarray(x, np.float32)
         y = None if y is None else np.ascontiguousarray(y, np.float64)
         self._check(self.lib.dispatch_set_start(self.h, int(s), _ptr(x, C.c_float), _ptr(y, C.c_double)),
                     allow_nc=False)
+
+
+def _check_dev(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+
+
+class MLP:
+    """The warm-start network in the library (BF16 MFMA GEMMs, Adam)."""
+
+    def __init__(self, n_in, width, hidden_layers, n_out, seed=0, stream=None):
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.mlp_init(C.byref(h), int(n_in), int(width), int(hidden_layers), int(n_out), int(seed),
+                               stream if stream is not None else None)
+        if rc != GP_OK:
+            raise GridplanError(rc, self.lib.mlp_last_error(None).decode())
+        self.h = h
+        n = C.c_int64()
+        self.lib.mlp_num_params(self.h, C.byref(n))
+        self.n_params = int(n.value)
+        self.dims = [int(n_in)] + [int(width)] * int(hidden_layers) + [int(n_out)]
+
+    def _check(self, rc):
+        if rc != GP_OK:
+            raise GridplanError(rc, self.lib.mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        w = np.zeros(self.n_params, np.float32)
+        self._check(self.lib.mlp_get_params(self.h, _ptr(w, C.c_float)))
+        return w
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.shape == (self.n_params,)
+        self._check(self.lib.mlp_set_params(self.h, _ptr(w, C.c_float)))
+
+    @staticmethod
+    def _arg(a):
+        if isinstance(a, np.ndarray):
+            a = np.ascontiguousarray(a, np.float32)
+            return a, C.c_void_p(a.ctypes.data), 0
+        _check_dev(a)
+        return a, C.c_void_p(a.data_ptr()), 1
+
+    def forward(self, X, Y=None):
+        Xk, xp, dev = self._arg(X)
+        rows = Xk.shape[0]
+        if Y is None:
+            if dev:
+                import torch
+                Y = torch.empty((rows, self.dims[-1]), dtype=torch.float32, device=Xk.device)
+            else:
+                Y = np.zeros((rows, self.dims[-1]), np.float32)
+        Yk, yp, ydev = self._arg(Y)
+        assert ydev == dev
+        self._check(self.lib.mlp_forward(self.h, xp, rows, dev, yp))
+        return Y
+
+    def loss_grad(self, X, T):
+        Xk, xp, dev = self._arg(X)
+        Tk, tp, tdev = self._arg(T)
+        assert tdev == dev
+        loss = C.c_double()
+        g = np.zeros(self.n_params, np.float32)
+        self._check(self.lib.mlp_loss_grad(self.h, xp, tp, Xk.shape[0], dev, C.byref(loss), _ptr(g, C.c_float)))
+        return float(loss.value), g
+
+    def adam_step(self, X, T, lr):
+        Xk, xp, dev = self._arg(X)
+        Tk, tp, tdev = self._arg(T)
+        assert tdev == dev
+        loss = C.c_double()
+        self._check(self.lib.mlp_adam_step(self.h, xp, tp, Xk.shape[0], dev, float(lr), C.byref(loss)))
+        return float(loss.value)
+
+
+def gemm_test(A, B, M, N, K, ta=False, tb=False):
+    """C = op(A) op(B) through the library's BF16 MFMA GEMM (host arrays)."""
+    lib = load()
+    A = np.ascontiguousarray(A, np.float32)
+    B = np.ascontiguousarray(B, np.float32)
+    Cm = np.zeros((M, N), np.float32)
+    rc = lib.mlp_gemm_test(_ptr(A, C.c_float), _ptr(B, C.c_float), _ptr(Cm, C.c_float), M, N, K, int(ta), int(tb))
+    if rc != GP_OK:
+        raise GridplanError(rc, lib.mlp_last_error(None).decode())
+    return Cm

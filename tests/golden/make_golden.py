@@ -13,7 +13,8 @@ gradient of h_s (not weighted) as JSON:
 The spread is the largest relative change of the oracle gradient when every
 capacity moves by U[-0.02, 0.02] MW (two draws): the GPU solves to a balance
 residual of about that size, so near a kink of the piecewise-affine dispatch
-map its gradient cannot be more accurate than this.
+map its gradient cannot be more accurate than this.  The moved gradients are
+stored too, so a test can take the same measure on any subset of capacities.
 """
 import json
 import os
@@ -49,14 +50,17 @@ def spread(cfg, s):
     g0 = np.array(out["grad"])
     net = case.scenarios[s].network
     worst = 0.0
+    moved = []
     for k in range(2):
         rng = np.random.Generator(np.random.PCG64(1000 + k))
         ep = np.clip(eta + rng.uniform(-SPREAD_MW, SPREAD_MW, size=eta.shape), case.eta_min(), case.eta_max())
         qp = D.assemble(case, s, ep[off[net]:off[net + 1]])
         sol = D.solve(qp)
         g = Gm.scenario_gradient(qp, sol, case.omega)["grad"]
+        moved.append([float(v) for v in g])
         worst = max(worst, float(np.linalg.norm(g - g0) / np.linalg.norm(g0)))
     out["grad_spread"] = worst
+    out["spread_grads"] = moved
     out["spread_mw"] = SPREAD_MW
     with open(path, "w") as fh:
         json.dump(out, fh)

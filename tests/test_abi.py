@@ -73,9 +73,17 @@ def test_plan_init_rejects_bad_case(mutate, needle):
     assert needle in msg
 
 
-def test_plan_init_rejects_bad_options():
-    rc, msg, _ = _init(cases.config0(), gpb.options(block=100))
-    assert rc == gpb.GP_EINVAL and "block" in msg
+@pytest.mark.parametrize("opts,needle", [
+    (dict(block=100), "block"),
+    (dict(variant=3), "variant"),
+    (dict(tol=-1.0), "negative"),
+    (dict(stall_pct=-5), "negative"),
+    (dict(accept_warm=2), "accept_warm"),
+    (dict(rho0=float("inf")), "finite"),
+])
+def test_plan_init_rejects_bad_options(opts, needle):
+    rc, msg, _ = _init(cases.config0(), gpb.options(**opts))
+    assert rc == gpb.GP_EINVAL and needle in msg
 
 
 def test_null_arguments():
