@@ -160,6 +160,143 @@ def summarize(stats_csv, fetch_csv, write_csv, pmc_line, workload_id, commands):
     return "\n".join(out) + "\n"
 
 
+def warm_start_leg(args):
+    """s/gradient step on the 1000-node workload, cold vs learned warm (with
+    the previous-iterate warm start as the extra baseline).
+
+    Protocol (projected SGD as in Section 3.2: a pool of scenarios, a batch
+    sampled per step): training data come from planning runs under four
+    storage capital costs; the held-out run uses a fifth cost.  Every arm
+    of the held-out run samples the same batches; a step is solve (to the
+    1e-4 KKT residual) + gradient + projected update, timed end to end, the
+    learned arm including feature extraction, inference and seeding."""
+    import numpy as np
+    import torch
+
+    from paper_2410_13055_amd import cases, gridplan
+    from paper_2410_13055_amd.warmstart import LearnedWarmStart
+
+    case = cases.config4()
+    net = case.networks[0]
+    G, L, N, T = net.n_gens, net.n_lines, net.n_nodes, case.scenarios[0].T
+    pool, B, steps = list(range(args.ws_pool)), args.ws_batch, args.ws_steps
+    lo, hi = case.eta_min(), case.eta_max()
+    log = lambda *a: print("[warm]", *a, file=sys.stderr, flush=True)  # noqa: E731
+
+    def gamma_for(price):
+        g = case.gamma().copy()
+        g[G + L:] = cases.storage_gamma_per_mw(price)
+        return g
+
+    def batches(seed):
+        rng = np.random.default_rng(seed)
+        return [sorted(rng.choice(pool, B, replace=False).tolist()) for _ in range(steps)]
+
+    # one tuning pass fixes the sweep configuration for every plan
+    probe = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
+    probe.solve(lo, pool[:B])
+    tb, tv, tce, _ = probe.tuning()
+    probe.close()
+    opts = dict(block=tb, variant=tv, check_every=tce)
+    log(f"sweep configuration: block {tb}, form {tv}, {tce} iterations per replay")
+
+    plan = gridplan.Plan(case, gridplan.options(**opts), stream=gridplan.current_stream())
+    ws = LearnedWarmStart(plan, T, seed=0)
+    held_price = args.ws_held_price
+    plan.solve(lo, pool[:B], warm=0)
+    g0, _, _ = plan.grad(pool[:B])
+    alpha = 0.05 * float((hi - lo).min()) / float(np.abs(gamma_for(held_price) + g0).max())
+
+    def run(p, price, seed, arm, collect=False):
+        gam = gamma_for(price)
+        eta = lo.copy()
+        out = {"s": [], "iters": [], "starts": [], "kkt": []}
+        for k, scen in enumerate(batches(seed)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if arm == "learned":
+                ws.seed(eta, scen)
+            _, st, rc = p.solve(eta, scen, warm=0 if arm == "cold" else 1)
+            g, _, _ = p.grad(scen)
+            if collect:
+                ws.collect(eta, scen)
+            eta = np.clip(eta - alpha * (gam + g), lo, hi)
+            torch.cuda.synchronize()
+            out["s"].append(time.perf_counter() - t0)
+            out["iters"].append(max(x["iters"] for x in st))
+            out["starts"] += [x["start"] for x in st]
+            out["kkt"].append(max(x["kkt"] for x in st))
+            log(f"{arm} price {price} step {k}: {out['s'][-1]:.2f} s, iterations {out['iters'][-1]}, "
+                f"starts {[x['start'] for x in st]}")
+        out["eta"] = eta
+        return out
+
+    t0 = time.perf_counter()
+    for i, price in enumerate(args.ws_train_prices):
+        run(plan, price, 100 + i, "previous", collect=True)
+    collect_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = ws.train(epochs=args.ws_epochs, batch_rows=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained on {ws.rows} rows: loss {losses[0]:.4f} -> {losses[-1]:.4f} in {train_s:.1f} s")
+
+    arms = {}
+    for arm in ("cold", "previous", "learned"):
+        p = plan if arm == "learned" else gridplan.Plan(case, gridplan.options(**opts),
+                                                        stream=gridplan.current_stream())
+        arms[arm] = run(p, held_price, 999, arm)
+        if p is not plan:
+            p.close()
+    # inference GEMMs: MFMA roofline of the network's forward pass
+    rows = B * N
+    X = ws.features(lo, pool[:B])
+    ws.net.forward(X)
+    ms = ws.net.time_forward(rows, 20)
+    flops = ws.net.flops_per_row() * rows
+    tflops = flops / (ms * 1e-3) / 1e12
+    plan.close()
+
+    def summary(a):
+        return {"s_per_step_median": round(float(np.median(a["s"])), 4),
+                "s_per_step": [round(x, 3) for x in a["s"]],
+                "iterations_max_per_step": a["iters"],
+                "starts": {str(k): a["starts"].count(k) for k in sorted(set(a["starts"]))},
+                "kkt_max": float(max(a["kkt"]))}
+    med = {k: float(np.median(v["s"])) for k, v in arms.items()}
+    drift = float(np.abs(arms["learned"]["eta"] - arms["cold"]["eta"]).max())
+    out = {
+        "metric": "s/gradient step, cold vs learned warm",
+        "value": round(med["learned"], 4),
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "ms_per_step": round(med["learned"] * 1e3, 1),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 solve / bf16 MLP",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[4] + f"; batch of {B} sampled per step from the first "
+                               f"{len(pool)} scenarios; held-out storage cost {held_price} $/kWh",
+                   "tol": 1e-4, "alpha": alpha},
+        "speedup_cold_over_learned": round(med["cold"] / med["learned"], 3),
+        "speedup_cold_over_previous": round(med["cold"] / med["previous"], 3),
+        "arms": {k: summary(v) for k, v in arms.items()},
+        "max_eta_difference_learned_vs_cold_MW": drift,
+        "training": {"storage_costs": args.ws_train_prices, "steps_per_run": steps, "rows": ws.rows,
+                     "epochs": args.ws_epochs, "loss_first": losses[0], "loss_last": losses[-1],
+                     "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
+                     "network": f"{5 * T + 3} -> 512 x3 -> {2 * T}, {ws.net.n_params} parameters"},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm (network forward, 4 layers)",
+                     "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 5), "traffic": None, "rows": rows,
+                     "ms_per_forward": round(ms, 5)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +309,14 @@ def main():
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: one iteration chunk, 10 timed sweeps of "
                          "each kernel and a 1 GiB device copy that calibrates the byte counters")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="s/gradient step on the 1000-node workload: cold vs learned warm vs previous-iterate")
+    ap.add_argument("--ws-pool", type=int, default=16)
+    ap.add_argument("--ws-batch", type=int, default=4)
+    ap.add_argument("--ws-steps", type=int, default=6)
+    ap.add_argument("--ws-epochs", type=int, default=150)
+    ap.add_argument("--ws-train-prices", type=float, nargs="+", default=[100.0, 175.0, 325.0, 400.0])
+    ap.add_argument("--ws-held-price", type=float, default=250.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
@@ -186,6 +331,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.warm_start:
+        warm_start_leg(args)
+        return
     case = cases.by_id(args.config)
     scen = list(range(len(case.scenarios)))
     sh = case.scenario_hours(scen)

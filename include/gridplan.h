@@ -111,7 +111,7 @@ typedef struct {
   int32_t variant;       /* sweep form: 0 tuned, 1 one block per tile,
                             2 persistent work queue */
   int32_t accept_warm;   /* 1 = take every warm start as given: no
-                            residual screen, no stall limit [0] */
+                            dual screen, no stall limit [0] */
   int32_t stall_pct;     /* stall limit of a warm start, in percent of the
                             iterations of the network's last converged
                             cold solve; 0 = 100 [0] */
@@ -124,8 +124,8 @@ typedef struct {
   int32_t restarts;  /* restarts taken */
   int32_t status;    /* 0 converged, 1 iteration limit */
   int32_t start;     /* 0 cold, 1 warm, 2 warm start screened out (its
-                        KKT residual was above 100 times the cold
-                        start's), 3 warm start abandoned for a cold
+                        dual point scored below zero on the exact dual
+                        function), 3 warm start abandoned for a cold
                         start after the stall limit */
   double r_pri, r_dual, r_gap, kkt;  /* relative KKT residual parts (FP64) */
   double cost;       /* c_s(x) at the returned point */
@@ -152,9 +152,9 @@ int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void
  * scen: [nb] distinct scenario indices.  warm_mode: 0 cold start (x = 0,
  * y = 0), 1 start from each scenario's stored point: its last solution, or
  * the point plan_start_from_prediction seeded; scenarios without a stored
- * point start cold.  Per scenario, a warm start whose KKT residual (the
- * stopping norm) exceeds 100 times the cold start's is replaced by the cold
- * start (stats.start = 2), and one that has not converged within the
+ * point start cold.  Per scenario, a warm start whose dual point has a
+ * lower exact dual function value than y = 0 is replaced by the cold start
+ * (stats.start = 2), and one that has not converged within the
  * iterations of the last converged cold solve on the same network (times
  * opt.stall_pct / 100) restarts cold (stats.start = 3; iters counts both
  * parts).
@@ -230,10 +230,12 @@ int plan_features(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb
 int plan_targets(gp_plan* p, const int32_t* scen, int32_t nb, float* Y_dev);
 
 /* Seed the listed scenarios' next warm_mode = 1 solve from a prediction
- * P_dev [rows x 2T] in the target encoding: prices become the balance duals,
+ * P_dev [rows x 2T] in the target encoding: prices, clipped to
+ * [0, lambda_u], become the balance duals,
  * angles the bus angles, flows the clipped DC flows of those angles,
- * generators and unserved load their best response to the price, flow duals
- * the lines' stationarity at that flow, batteries and SOC duals zero. */
+ * generators their best response to the price, unserved load its best
+ * response capped at the node's load; flow duals, batteries and SOC duals
+ * zero. */
 int plan_start_from_prediction(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb,
                                const float* P_dev);
 
@@ -257,6 +259,22 @@ int mlp_loss_grad(gp_mlp* m, const float* X, const float* T, int64_t rows, int32
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error. */
 int mlp_adam_step(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device, double lr,
                   double* loss);
+/* Standardisation of inputs and targets: column means and standard
+ * deviations (FP64 sums; a column without spread keeps sd 1) of X [rows x
+ * n_in] and T [rows x n_out].  From then on the network sees (x - mu)/sd,
+ * is trained on (y - mu)/sd (the loss is in those units) and mlp_forward
+ * returns predictions in target units. */
+int mlp_fit_scaling(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device);
+/* Read (host arrays, each nullable) or set (host arrays, sd > 0) the
+ * scaling.  GP_ESTATE from the getter when none is set. */
+int mlp_get_scaling(gp_mlp* m, float* x_mu, float* x_sd, float* y_mu, float* y_sd);
+int mlp_set_scaling(gp_mlp* m, const float* x_mu, const float* x_sd, const float* y_mu, const float* y_sd);
+/* Mean HIP-event time (ms) of one forward pass (the layer GEMMs with their
+ * bias/ReLU epilogues) over the first `rows` rows of the input loaded by the
+ * last forward / loss / Adam call, `iters` passes back to back on the
+ * network's stream; a measurement aid.  GP_ESTATE when fewer rows are
+ * loaded. */
+int mlp_time_forward(gp_mlp* m, int64_t rows, int32_t iters, double* ms_out);
 /* C [M x N] = op(A) op(B) through the same BF16 MFMA kernel (host FP32 in,
  * rounded to BF16; op = transpose when ta / tb).  A is [M x K] or [K x M],
  * B [K x N] or [N x K]. */

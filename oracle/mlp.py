@@ -13,6 +13,11 @@ network and its feature extraction compute, in plain numpy:
   output gradients) rounded to BF16, products accumulated exactly (FP64),
   biases and the loss in full precision.  ``rounding=False`` gives the
   unrounded FP64 network used for the finite-difference pin.
+* ``colstats`` and ``scaling``: optional standardisation of inputs and
+  targets by column mean and standard deviation.  The network then sees
+  (x - mu_x)/sd_x (FP32 arithmetic, then BF16), is trained on
+  (y - mu_y)/sd_y (the loss is in those units) and ``forward`` returns
+  predictions in target units.
 * ``features`` / ``targets``: the per-node inputs and outputs of the network
   for one scenario (same definitions as the library's documentation).
 """
@@ -48,10 +53,32 @@ def unpack(params, dims):
     return W, B
 
 
-def forward(params, dims, X, rounding=True):
+def colstats(A):
+    """Column mean and population standard deviation of A, as FP32; a column
+    whose spread is below 1e-6 (1 + |mean|) keeps sd = 1 (it is only
+    centred)."""
+    A = np.asarray(A, np.float64)
+    mu = A.mean(axis=0)
+    sd = np.sqrt(np.maximum((A * A).mean(axis=0) - mu * mu, 0.0))
+    sd = np.where(sd > 1e-6 * (1.0 + np.abs(mu)), sd, 1.0)
+    return mu.astype(np.float32), sd.astype(np.float32)
+
+
+def scaling(X, T):
+    """(x_mu, x_sd, y_mu, y_sd) of a training set."""
+    return (*colstats(X), *colstats(T))
+
+
+def _standardise(A, mu, sd):
+    """(A - mu) * (1/sd) in FP32 arithmetic."""
+    A = np.asarray(A, np.float32)
+    return ((A - np.float32(1) * mu) * (np.float32(1) / sd)).astype(np.float32).astype(np.float64)
+
+
+def _net(params, dims, X, rounding, sc):
     r = bf16 if rounding else (lambda v: np.asarray(v, np.float64))
     W, B = unpack(params, dims)
-    h = r(X)
+    h = r(_standardise(X, sc[0], sc[1]) if sc is not None else X)
     acts = [h]
     L = len(W)
     for l in range(L):
@@ -64,12 +91,21 @@ def forward(params, dims, X, rounding=True):
     return y, acts
 
 
-def loss_grad(params, dims, X, T, rounding=True):
-    """Mean squared error over every output and its gradient (flat)."""
+def forward(params, dims, X, rounding=True, sc=None):
+    """Network output in target units (and the BF16 activations)."""
+    z, acts = _net(params, dims, X, rounding, sc)
+    if sc is not None:
+        z = (np.asarray(z, np.float32) * sc[3] + sc[2]).astype(np.float32).astype(np.float64)
+    return z, acts
+
+
+def loss_grad(params, dims, X, T, rounding=True, sc=None):
+    """Mean squared error over every output and its gradient (flat); with a
+    scaling, in standardised target units."""
     r = bf16 if rounding else (lambda v: np.asarray(v, np.float64))
     W, B = unpack(params, dims)
-    y, acts = forward(params, dims, X, rounding)
-    T = np.asarray(T, np.float64)
+    y, acts = _net(params, dims, X, rounding, sc)
+    T = _standardise(T, sc[2], sc[3]) if sc is not None else np.asarray(T, np.float64)
     n = y.size
     d = y - T
     loss = float(np.sum(d * d) / n)

@@ -994,8 +994,15 @@ __global__ void k_targets(Args a, const int32_t* bscen, int nb, const int32_t* r
 }
 
 // predicted node price and angle of (s, n, t)
-__device__ __forceinline__ double pred_price(const float* P, int64_t row, int T, int t) {
+// Prices are clipped to [0, lambda_u]: generation can always be curtailed
+// and unserved load caps the price at the penalty (up to r times the node's
+// unserved load), so every optimal price lies within that interval up to
+// that margin, and a prediction outside it only moves away.
+__device__ __forceinline__ double pred_price_raw(const float* P, int64_t row, int T, int t) {
   return 100.0 * sinh((double)P[row * 2 * T + t]);
+}
+__device__ __forceinline__ double pred_price(const float* P, int64_t row, int T, int t, double lambda_u) {
+  return fmin(fmax(pred_price_raw(P, row, T, t), 0.0), lambda_u);
 }
 __device__ __forceinline__ float pred_angle(const float* P, int64_t row, int T, int t) {
   return 10.f * P[row * 2 * T + T + t];
@@ -1026,14 +1033,13 @@ __global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, con
     const int i = tl.start + threadIdx.x;
     if (tl.cls == RC_BAL) {
       const int n = i / T, t = i - n * T;
-      yh[i] = pred_price(P, r0 + n, T, t);
-    } else {  // flow dual from the line's stationarity at the clipped flow
-      const int l = i / T, t = i - l * T;
-      const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-      const float cap = a.eta[nt.eta_off + nt.G + l];
-      const float b = a.line_beta[nt.line_off + l];
-      const float f = clampf(b * (pred_angle(P, r0 + fr, T, t) - pred_angle(P, r0 + to, T, t)), -cap, cap);
-      yh[(int64_t)nt.N * TT + i] = r * f - (pred_price(P, r0 + to, T, t) - pred_price(P, r0 + fr, T, t));
+      yh[i] = pred_price(P, r0 + n, T, t, a.lambda_u);
+    } else {
+      // Flow duals start at zero.  Taking them from the line's stationarity
+      // at the predicted prices is exact for uncongested lines but wrong for
+      // congested ones (their bound multiplier takes the price difference),
+      // and the wrong ones leave a large angle residual; zero measured faster.
+      yh[(int64_t)nt.N * TT + i] = 0.0;
     }
     return;
   }
@@ -1044,7 +1050,7 @@ __global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, con
       const int g = i / T, t = i - g * T;
       const int n = a.gen_node[nt.gen_off + g];
       const double hi = (double)a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
-      const double p = (pred_price(P, r0 + n, T, t) - a.gen_cost[nt.gen_off + g]) / r;
+      const double p = (pred_price(P, r0 + n, T, t, a.lambda_u) - a.gen_cost[nt.gen_off + g]) / r;
       xh[i] = (float)fmin(fmax(p, 0.0), hi);
       break;
     }
@@ -1062,7 +1068,7 @@ __global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, con
       xh[(int64_t)(nt.G + nt.L) * TT + i] = pred_angle(P, r0 + n, T, t);
       // unserved load: best response, at most the node's load (a price
       // just above the penalty would otherwise ask for (pi - lambda_u)/r)
-      const double u = (pred_price(P, r0 + n, T, t) - a.lambda_u) / r;
+      const double u = (pred_price_raw(P, r0 + n, T, t) - a.lambda_u) / r;
       const double dmax = fmax((double)a.load[sc.doff + (int64_t)n * TT + t], 0.0);
       xh[(int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i] = (float)fmin(fmax(u, 0.0), dmax);
       break;

@@ -139,14 +139,75 @@ __global__ void k_cast_bf16(const float* __restrict__ x, __bf16* __restrict__ y,
   if (i < n) y[i] = to_bf16(x[i]);
 }
 
-// dY = (2 / count) (Y - T) per element, loss partials per block (FP64)
+// input standardisation fused into the cast: y = bf16((x - mu[c]) * isd[c])
+__global__ void k_cast_std(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n, int ncol,
+                           const float* __restrict__ mu, const float* __restrict__ isd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % ncol);
+  y[i] = to_bf16((x[i] - mu[c]) * isd[c]);
+}
+
+// network output back in target units: Y = Z * sd[c] + mu[c]
+__global__ void k_unscale(const float* __restrict__ Z, float* __restrict__ Y, int64_t n, int ncol,
+                          const float* __restrict__ mu, const float* __restrict__ sd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % ncol);
+  Y[i] = Z[i] * sd[c] + mu[c];
+}
+
+// column sums and sums of squares over one chunk of rows (FP64)
+__global__ void k_colstats_part(const float* __restrict__ X, int64_t rows, int ncol, int64_t chunk,
+                                double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk, r1 = r0 + chunk < rows ? r0 + chunk : rows;
+  double s = 0.0, q = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double v = X[r * ncol + c];
+    s += v;
+    q += v * v;
+  }
+  part[(int64_t)(2 * blockIdx.y) * ncol + c] = s;
+  part[(int64_t)(2 * blockIdx.y + 1) * ncol + c] = q;
+}
+
+// mean and standard deviation per column (chunks summed in order); a column
+// with (numerically) no spread keeps sd = 1 and is only centred
+__global__ void k_colstats_final(const double* __restrict__ part, int nchunk, int ncol, int64_t rows,
+                                 float* __restrict__ mu, float* __restrict__ sd, float* __restrict__ isd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0, q = 0.0;
+  for (int k = 0; k < nchunk; ++k) {
+    s += part[(int64_t)(2 * k) * ncol + c];
+    q += part[(int64_t)(2 * k + 1) * ncol + c];
+  }
+  const double m = s / (double)rows;
+  const double v = fmax(q / (double)rows - m * m, 0.0);
+  double d = sqrt(v);
+  if (!(d > 1e-6 * (1.0 + fabs(m)))) d = 1.0;
+  mu[c] = (float)m;
+  sd[c] = (float)d;
+  isd[c] = 1.f / (float)d;
+}
+
+// dY = (2 / count) (Y - T') per element with T' = (T - mu[c]) * isd[c] when
+// the targets are standardised (mu non-null); loss partials per block (FP64)
 __global__ void k_mse(const float* __restrict__ Y, const float* __restrict__ T, float* __restrict__ dY,
-                      __bf16* __restrict__ dYb, double* __restrict__ part, int64_t n, double scale) {
+                      __bf16* __restrict__ dYb, double* __restrict__ part, int64_t n, double scale, int ncol,
+                      const float* __restrict__ mu, const float* __restrict__ isd) {
   __shared__ double sh[256];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double l = 0.0;
   if (i < n) {
-    const float d = Y[i] - T[i];
+    float t = T[i];
+    if (mu) {
+      const int c = (int)(i % ncol);
+      t = (t - mu[c]) * isd[c];
+    }
+    const float d = Y[i] - t;
     l = (double)d * d;
     const float g = (float)(2.0 * scale) * d;
     dY[i] = g;
@@ -271,6 +332,12 @@ struct gp_mlp {
   Buf<float> gf;                 // FP32 gradient wrt a hidden activation (largest width)
   Buf<__bf16> gb0, gb1;          // BF16 gradients (ping-pong)
   Buf<double> part;
+  int64_t loaded_rows = 0;  // rows of the input last cast into act[0]
+  // standardisation of inputs and targets (set by mlp_fit_scaling /
+  // mlp_set_scaling): the network works on (x - x_mu)/x_sd and predicts
+  // (y - y_mu)/y_sd
+  bool scaled = false;
+  Buf<float> xmu, xsd, xisd, ymu, ysd, yisd;
   ~gp_mlp() {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
@@ -319,9 +386,14 @@ void load_input(gp_mlp* m, const float* X, int64_t rows, int on_device) {
     MCHK(hipMemcpyAsync(tmp.p, X, n * sizeof(float), hipMemcpyHostToDevice, m->stream));
     src = tmp.p;
   }
-  hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(n)), dim3(256), 0, m->stream, src, m->act[0].p, n);
+  if (m->scaled)
+    hipLaunchKernelGGL(k_cast_std, dim3(nblk(n)), dim3(256), 0, m->stream, src, m->act[0].p, n, m->dims[0],
+                       m->xmu.p, m->xisd.p);
+  else
+    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(n)), dim3(256), 0, m->stream, src, m->act[0].p, n);
   MCHK(hipGetLastError());
   if (!on_device) MCHK(hipStreamSynchronize(m->stream));
+  m->loaded_rows = rows;
 }
 
 // mean squared error over rows x n_out and the parameter gradient in m->g
@@ -338,7 +410,7 @@ double loss_backward(gp_mlp* m, const float* Tgt, int64_t rows, int on_device) {
   }
   const int nb = nblk(n);
   hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, m->out.p, t, m->dy.p, m->gb0.p, m->part.p, n,
-                     1.0 / (double)n);
+                     1.0 / (double)n, nout, m->scaled ? m->ymu.p : nullptr, m->scaled ? m->yisd.p : nullptr);
   MCHK(hipGetLastError());
   // layer L-1 .. 0
   float* gcur_f = m->dy.p;
@@ -384,6 +456,32 @@ int mguard(gp_mlp* m, const std::function<int()>& f) {
     if (m) m->err = e.msg;
     return e.code;
   }
+}
+}  // namespace
+
+namespace {
+void alloc_scaling(gp_mlp* m) {
+  const int ni = m->dims[0], no = m->dims.back();
+  m->xmu.alloc(ni);
+  m->xsd.alloc(ni);
+  m->xisd.alloc(ni);
+  m->ymu.alloc(no);
+  m->ysd.alloc(no);
+  m->yisd.alloc(no);
+}
+
+void colstats(gp_mlp* m, const float* X, int64_t rows, int ncol, float* mu, float* sd, float* isd) {
+  // rows per chunk: at least 2048, and few enough chunks for the grid
+  const int64_t chunk = std::max<int64_t>(2048, (rows + 65534) / 65535);
+  const int nchunk = (int)((rows + chunk - 1) / chunk);
+  Buf<double> part;
+  part.alloc((size_t)2 * nchunk * ncol);
+  hipLaunchKernelGGL(k_colstats_part, dim3(nblk(ncol), nchunk), dim3(256), 0, m->stream, X, rows, ncol, chunk,
+                     part.p);
+  hipLaunchKernelGGL(k_colstats_final, dim3(nblk(ncol)), dim3(256), 0, m->stream, part.p, nchunk, ncol, rows, mu,
+                     sd, isd);
+  MCHK(hipGetLastError());
+  MCHK(hipStreamSynchronize(m->stream));
 }
 }  // namespace
 
@@ -486,7 +584,14 @@ int mlp_forward(gp_mlp* m, const float* X, int64_t rows, int32_t on_device, floa
     load_input(m, X, rows, on_device);
     forward(m, rows);
     const int64_t n = rows * m->dims.back();
-    MCHK(hipMemcpyAsync(Y, m->out.p, n * sizeof(float), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+    const float* src = m->out.p;
+    if (m->scaled) {  // back to target units, in place in the dY buffer
+      hipLaunchKernelGGL(k_unscale, dim3(nblk(n)), dim3(256), 0, m->stream, m->out.p, m->dy.p, n, m->dims.back(),
+                         m->ymu.p, m->ysd.p);
+      MCHK(hipGetLastError());
+      src = m->dy.p;
+    }
+    MCHK(hipMemcpyAsync(Y, src, n * sizeof(float), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                         m->stream));
     MCHK(hipStreamSynchronize(m->stream));
     return GP_OK;
@@ -536,6 +641,97 @@ int mlp_adam_step(gp_mlp* m, const float* X, const float* T, int64_t rows, int32
                        m->v.p + nw, (__bf16*)nullptr, nbias, (float)lr, b1, b2, 1e-8f, c1, c2);
     MCHK(hipGetLastError());
     MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+
+int mlp_fit_scaling(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!X || !T) mfail(GP_EINVAL, "X and T must not be NULL");
+    check_dims(m, rows);
+    const int ni = m->dims[0], no = m->dims.back();
+    Buf<float> hx, ht;
+    const float *x = X, *t = T;
+    if (!on_device) {
+      hx.alloc((size_t)rows * ni);
+      ht.alloc((size_t)rows * no);
+      MCHK(hipMemcpyAsync(hx.p, X, (size_t)rows * ni * sizeof(float), hipMemcpyHostToDevice, m->stream));
+      MCHK(hipMemcpyAsync(ht.p, T, (size_t)rows * no * sizeof(float), hipMemcpyHostToDevice, m->stream));
+      x = hx.p;
+      t = ht.p;
+    }
+    alloc_scaling(m);
+    colstats(m, x, rows, ni, m->xmu.p, m->xsd.p, m->xisd.p);
+    colstats(m, t, rows, no, m->ymu.p, m->ysd.p, m->yisd.p);
+    m->scaled = true;
+    return GP_OK;
+  });
+}
+
+int mlp_get_scaling(gp_mlp* m, float* x_mu, float* x_sd, float* y_mu, float* y_sd) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!m->scaled) mfail(GP_ESTATE, "no scaling set");
+    const int ni = m->dims[0], no = m->dims.back();
+    auto get = [&](float* dst, const Buf<float>& b, int n) {
+      if (dst) MCHK(hipMemcpyAsync(dst, b.p, n * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    };
+    get(x_mu, m->xmu, ni);
+    get(x_sd, m->xsd, ni);
+    get(y_mu, m->ymu, no);
+    get(y_sd, m->ysd, no);
+    MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+int mlp_set_scaling(gp_mlp* m, const float* x_mu, const float* x_sd, const float* y_mu, const float* y_sd) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!x_mu || !x_sd || !y_mu || !y_sd) mfail(GP_EINVAL, "scaling arrays must not be NULL");
+    const int ni = m->dims[0], no = m->dims.back();
+    std::vector<float> xi(ni), yi(no);
+    for (int c = 0; c < ni; ++c) {
+      if (!std::isfinite(x_mu[c]) || !(x_sd[c] > 0.f) || !std::isfinite(x_sd[c])) mfail(GP_EINVAL, "bad input scaling");
+      xi[c] = 1.f / x_sd[c];
+    }
+    for (int c = 0; c < no; ++c) {
+      if (!std::isfinite(y_mu[c]) || !(y_sd[c] > 0.f) || !std::isfinite(y_sd[c])) mfail(GP_EINVAL, "bad target scaling");
+      yi[c] = 1.f / y_sd[c];
+    }
+    alloc_scaling(m);
+    MCHK(hipMemcpyAsync(m->xmu.p, x_mu, ni * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->xsd.p, x_sd, ni * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->xisd.p, xi.data(), ni * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->ymu.p, y_mu, no * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->ysd.p, y_sd, no * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipMemcpyAsync(m->yisd.p, yi.data(), no * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
+    m->scaled = true;
+    return GP_OK;
+  });
+}
+
+int mlp_time_forward(gp_mlp* m, int64_t rows, int32_t iters, double* ms_out) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    if (!ms_out || iters < 1) mfail(GP_EINVAL, "ms_out must not be NULL and iters >= 1");
+    if (rows < 1 || rows > m->loaded_rows) mfail(GP_ESTATE, "time only rows already loaded by a forward call");
+    hipEvent_t e0, e1;
+    MCHK(hipEventCreate(&e0));
+    MCHK(hipEventCreate(&e1));
+    forward(m, rows);  // untimed
+    MCHK(hipEventRecord(e0, m->stream));
+    for (int i = 0; i < iters; ++i) forward(m, rows);
+    MCHK(hipEventRecord(e1, m->stream));
+    MCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    MCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_out = ms / iters;
     return GP_OK;
   });
 }

@@ -841,10 +841,6 @@ Kkt kkt_of(const gp_plan* p, const double* st, double einf, double e2 = 0.0, dou
 
 // The restarted Halpern loop shared by the dispatch solve (mode 0) and the
 // adjoint solve (mode 1).  Returns the number of unconverged entries.
-// a warm start is screened out when its KKT residual exceeds this multiple
-// of the cold start's
-constexpr double kWarmScreen = 100.0;
-
 int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
             std::vector<gp_solve_stats>& out, double omega) {
   const std::vector<int>& batch = p->batch;
@@ -892,28 +888,36 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   if (n_warm < nb) reset_where(RESET_COLD, [&](int b) { return start[b] == 0; });
   if (n_warm > 0) reset_where(RESET_WARM, [&](int b) { return start[b] == 1; });
   if (n_warm > 0 && !p->opt.accept_warm) {
-    // Screen each warm start against the cold start: the residual at the
-    // warm point, then at zero (probe), then the warm point is put back and
-    // the scenarios whose warm residual exceeds kWarmScreen times the cold
-    // one go back to zeros (a NaN residual counts as worse).  The residual
-    // of a start does not rank starts by the work left (a point with exact
-    // prices but bang-bang generator outputs measures ~10-50 against ~1 at
-    // zero and still needs a fraction of the cold iterations), so the screen
-    // only removes predictions that are far off; the stall rule below
-    // bounds what an accepted start can cost.
+    // Screen each warm start against the cold start by the exact dual
+    // function D (concave, D <= the optimum, so D(y*) - D(y) is the dual
+    // suboptimality of y): measure it at the warm point, then at zero
+    // (probe), put the warm point back, and send the scenarios whose dual
+    // start is worse than zero back to zeros (NaN counts as worse).  The
+    // KKT residual of a start does not rank starts by the work left (any
+    // start with bang-bang generator outputs measures O(1), as zero does),
+    // so it is only reported; the stall rule below bounds what an accepted
+    // start can cost.
     run_check_only(p, a);
-    std::vector<double> kw(nb), kc(nb);
-    for (int b = 0; b < nb; ++b) kw[b] = stop_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+    std::vector<double> dw(nb), dc(nb), kw(nb), kc(nb);
+    for (int b = 0; b < nb; ++b) {
+      dw[b] = p->h_stats[(size_t)b * kStats + ST_D];
+      kw[b] = stop_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+    }
     reset_where(RESET_PROBE, [&](int b) { return start[b] == 1; });
     run_check_only(p, a);
-    for (int b = 0; b < nb; ++b) kc[b] = stop_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+    for (int b = 0; b < nb; ++b) {
+      dc[b] = p->h_stats[(size_t)b * kStats + ST_D];
+      kc[b] = stop_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
+    }
     reset_where(RESET_RESTORE, [&](int b) { return start[b] == 1; });
     bool any = false;
     for (int b = 0; b < nb; ++b) {
-      if (p->opt.verbose && start[b] == 1)
-        fprintf(stderr, "[gridplan] warm start of scenario %d: KKT %.3e, cold %.3e%s\n", batch[b], kw[b], kc[b],
-                kw[b] <= kWarmScreen * kc[b] ? "" : " (rejected)");
-      if (start[b] != 1 || kw[b] <= kWarmScreen * kc[b]) continue;
+      if (start[b] != 1) continue;
+      const bool ok = dw[b] >= dc[b];
+      if (p->opt.verbose)
+        fprintf(stderr, "[gridplan] warm start of scenario %d: dual %.6e (cold %.6e), KKT %.3e (cold %.3e)%s\n",
+                batch[b], dw[b], dc[b], kw[b], kc[b], ok ? "" : " (rejected)");
+      if (ok) continue;
       p->h_cw[batch[b]] = c0;
       p->h_cwf[batch[b]] = 1.f;
       start[b] = 2;

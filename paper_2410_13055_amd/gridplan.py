@@ -23,7 +23,8 @@ EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "plan_step",
            "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_tuning",
            "plan_nn_rows", "plan_features", "plan_targets", "plan_start_from_prediction",
            "mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
-           "mlp_loss_grad", "mlp_adam_step", "mlp_gemm_test", "mlp_free", "mlp_last_error",
+           "mlp_loss_grad", "mlp_adam_step", "mlp_fit_scaling", "mlp_get_scaling",
+           "mlp_set_scaling", "mlp_time_forward", "mlp_gemm_test", "mlp_free", "mlp_last_error",
            "plan_sizes", "plan_free", "plan_last_error")
 
 
@@ -126,6 +127,13 @@ def load(path: str = LIB_PATH):
                                   P(C.c_double), P(C.c_float)]
     lib.mlp_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
                                   P(C.c_double)]
+    lib.mlp_fit_scaling.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]
+    lib.mlp_get_scaling.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), P(C.c_float), P(C.c_float)]
+    lib.mlp_set_scaling.argtypes = [C.c_void_p, P(C.c_float), P(C.c_float), P(C.c_float), P(C.c_float)]
+    for f in ("mlp_fit_scaling", "mlp_get_scaling", "mlp_set_scaling"):
+        getattr(lib, f).restype = C.c_int
+    lib.mlp_time_forward.argtypes = [C.c_void_p, C.c_int64, C.c_int32, P(C.c_double)]
+    lib.mlp_time_forward.restype = C.c_int
     lib.mlp_gemm_test.argtypes = [P(C.c_float), P(C.c_float), P(C.c_float), C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int32, C.c_int32]
     for f in ("mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
@@ -437,6 +445,35 @@ class MLP:
         loss = C.c_double()
         self._check(self.lib.mlp_adam_step(self.h, xp, tp, Xk.shape[0], dev, float(lr), C.byref(loss)))
         return float(loss.value)
+
+
+    def fit_scaling(self, X, T):
+        """Standardise inputs and targets by the columns' mean and sd."""
+        Xk, xp, dev = self._arg(X)
+        Tk, tp, tdev = self._arg(T)
+        assert tdev == dev
+        self._check(self.lib.mlp_fit_scaling(self.h, xp, tp, Xk.shape[0], dev))
+
+    def get_scaling(self):
+        """(x_mu, x_sd, y_mu, y_sd) as host float32 arrays."""
+        ni, no = self.dims[0], self.dims[-1]
+        out = [np.zeros(ni, np.float32), np.zeros(ni, np.float32), np.zeros(no, np.float32),
+               np.zeros(no, np.float32)]
+        self._check(self.lib.mlp_get_scaling(self.h, *[_ptr(a, C.c_float) for a in out]))
+        return tuple(out)
+
+    def set_scaling(self, x_mu, x_sd, y_mu, y_sd):
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (x_mu, x_sd, y_mu, y_sd)]
+        self._check(self.lib.mlp_set_scaling(self.h, *[_ptr(a, C.c_float) for a in arrs]))
+
+    def time_forward(self, rows, iters=20):
+        """Mean ms of one forward pass over rows already loaded (HIP events)."""
+        ms = C.c_double()
+        self._check(self.lib.mlp_time_forward(self.h, int(rows), int(iters), C.byref(ms)))
+        return ms.value
+
+    def flops_per_row(self):
+        return 2 * sum(a * b for a, b in zip(self.dims[:-1], self.dims[1:]))
 
 
 def gemm_test(A, B, M, N, K, ta=False, tb=False):

@@ -29,6 +29,7 @@ class LearnedWarmStart:
                                 stream=gridplan.current_stream())
         self.X, self.Y = [], []
         self.history = []
+        self.scaled = False
 
     @property
     def rows(self):
@@ -55,11 +56,16 @@ class LearnedWarmStart:
         self.Y.append(Y)
 
     def train(self, epochs: int = 20, batch_rows: int = 4096, lr: float = 1e-3, seed: int = 0):
-        """Adam on the mean squared error over the collected rows; minibatches
-        are contiguous row ranges visited in a shuffled order."""
+        """Adam on the mean squared error over the collected rows, inputs and
+        targets standardised by the statistics of the data at the first
+        call; minibatches are contiguous row ranges visited in a shuffled
+        order.  Returns the mean loss per epoch (standardised units)."""
         torch = self.torch
         X = torch.cat(self.X) if len(self.X) > 1 else self.X[0]
         Y = torch.cat(self.Y) if len(self.Y) > 1 else self.Y[0]
+        if not self.scaled:
+            self.net.fit_scaling(X, Y)
+            self.scaled = True
         n = X.shape[0]
         starts = np.arange(0, n, batch_rows)
         rng = np.random.default_rng(seed)
