@@ -160,6 +160,30 @@ def summarize(stats_csv, fetch_csv, write_csv, pmc_line, workload_id, commands):
     return "\n".join(out) + "\n"
 
 
+def hbm_case_sweeps(iters):
+    """The sweep kernels on a working set far above the 256 MB Infinity
+    Cache: 16 scenarios of the 1000-node workload (a GPU's share of its 128),
+    timed with HIP events after a 64-iteration solve."""
+    from paper_2410_13055_amd import cases, gridplan
+
+    case = cases.config4()
+    scen = list(range(16))
+    plan = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
+    plan.solve(case.eta_min(), scen)
+    md, mp = plan.time_sweeps(scen, iters)
+    tb, tv, _, _ = plan.tuning()
+    plan.close()
+    ab = algorithmic_bytes(case, scen)
+    sfx = "_q" if tv == 2 else ""
+    res = {"workload": "geo1000, 16 of its 128 scenarios", "block": tb,
+           "form": "work queue" if tv == 2 else "tile grid"}
+    for k, ms, nb in (("k_primal" + sfx, mp, ab["primal"]), ("k_dual" + sfx, md, ab["dual"])):
+        gbs = nb / (ms * 1e-3) / 1e9
+        res[k] = {"ms_per_launch": round(ms, 5), "bytes_per_launch": nb, "achieved_GBs": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return res
+
+
 def warm_start_leg(args):
     """s/gradient step on the 1000-node workload, cold vs learned warm (with
     the previous-iterate warm start as the extra baseline).
@@ -309,6 +333,8 @@ def main():
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: one iteration chunk, 10 timed sweeps of "
                          "each kernel and a 1 GiB device copy that calibrates the byte counters")
+    ap.add_argument("--no-hbm-case", dest="hbm_case", action="store_false",
+                    help="skip timing the sweeps on 16 scenarios of the 1000-node workload")
     ap.add_argument("--warm-start", action="store_true",
                     help="s/gradient step on the 1000-node workload: cold vs learned warm vs previous-iterate")
     ap.add_argument("--ws-pool", type=int, default=16)
@@ -423,6 +449,8 @@ def main():
                   "kkt_max": float(np.max(kkts)),
                   "solve_only_scenario_hours_per_s": round(args.steps * sh / solve_s, 2)},
     }
+    if args.hbm_case:
+        out["extra"]["hbm_case"] = hbm_case_sweeps(args.sweep_iters)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_hours)

@@ -30,6 +30,11 @@ constexpr int kMaxStats = 5;  // slots [0, kMaxStats) are maxima, the rest sums
 enum VarClass { VC_GEN = 0, VC_LINE = 1, VC_NODE = 2, VC_BATT = 3 };
 // work classes of the dual (row) sweep
 enum RowClass { RC_BAL = 0, RC_FLOW = 1, RC_SOC = 2 };
+// work-queue counters: one per XCD, kQueueStride u64 words apart; a sweep
+// uses kQueueWords words (dual sweep first, then the primal sweep)
+constexpr int kXcd = 8;
+constexpr int kQueueStride = 16;
+constexpr int kQueueWords = kXcd * kQueueStride;
 enum ResetMode { RESET_WARM = 0, RESET_COLD = 1, RESET_PROBE = 2, RESET_RESTORE = 3 };
 
 struct Tile {
@@ -84,7 +89,7 @@ struct Args {
   const Tile* rtiles;  // row-sweep tiles
   int32_t nvt, nrt;
   int32_t mode;        // 0 dispatch, 1 adjoint (active entries fixed, free elsewhere)
-  int32_t pad0;
+  int32_t qgrab;       // work-queue form: tiles taken per counter update
   // network data
   const int32_t* gen_node;
   const float* gen_cost;

@@ -284,12 +284,46 @@ __global__ __launch_bounds__(BS) void k_primal(Args a, int j, int check) {
 // A fixed grid of resident blocks takes tiles from a 64-bit counter until the
 // queue is drained (every block exits once a fetch passes the tile count); the
 // last block to leave resets the counter pair for the next launch.
+// Persistent work queue: one counter per XCD (kQueueStride apart, so each
+// sits on its own cache line), each over the contiguous tile range that the
+// XCD-aware block remap gives that XCD.  A block works its home XCD's range
+// (blockIdx mod 8, the hardware's round-robin placement) `grab` tiles per
+// atomic, then steals from the other ranges in turn; the last block out
+// resets the counters for the next launch.
+
+__device__ __forceinline__ void queue_range(int x, int ntiles, int& lo, int& hi) {
+  const int per = ntiles / kXcd, rem = ntiles % kXcd;
+  lo = x * per + min(x, rem);
+  hi = lo + per + (x < rem ? 1 : 0);
+}
+
 __device__ __forceinline__ void queue_done(unsigned long long* qc, unsigned int* qd) {
   if (threadIdx.x == 0) {
     __threadfence();
     if (atomicAdd(qd, 1u) == gridDim.x - 1) {
-      atomicExch(qc, 0ULL);
+      for (int x = 0; x < kXcd; ++x) atomicExch(qc + x * kQueueStride, 0ULL);
       atomicExch(qd, 0u);
+    }
+  }
+}
+
+// run `work(tile)` over every tile of [0, ntiles) exactly once across the grid
+template <class F>
+__device__ __forceinline__ void queue_loop(int ntiles, int grab, unsigned long long* qc, F&& work) {
+  __shared__ long long cur;
+  const int home = blockIdx.x % kXcd;
+  for (int q = 0; q < kXcd; ++q) {
+    const int x = (home + q) % kXcd;
+    int lo, hi;
+    queue_range(x, ntiles, lo, hi);
+    for (;;) {
+      if (threadIdx.x == 0) cur = (long long)atomicAdd(qc + x * kQueueStride, (unsigned long long)grab);
+      __syncthreads();
+      const long long t0 = lo + cur;
+      __syncthreads();
+      if (t0 >= hi) break;
+      const int t1 = (int)min((long long)hi, t0 + grab);
+      for (int t = (int)t0; t < t1; ++t) work(t);
     }
   }
 }
@@ -298,30 +332,20 @@ template <int BS, int TAG>
 __global__ __launch_bounds__(BS) void k_dual_q(Args a, int j, int check, unsigned long long* qc,
                                                unsigned int* qd) {
   extern __shared__ float sres[];
-  __shared__ long long cur;
-  for (;;) {
-    if (threadIdx.x == 0) cur = (long long)atomicAdd(qc, 1ULL);
+  queue_loop(a.nrt, a.qgrab, qc, [&](int t) {
+    dual_tile<BS>(a, t, j, check, sres);
     __syncthreads();
-    const long long t = cur;
-    if (t >= a.nrt) break;
-    dual_tile<BS>(a, (int)t, j, check, sres);
-    __syncthreads();
-  }
+  });
   queue_done(qc, qd);
 }
 
 template <int BS, int TAG>
 __global__ __launch_bounds__(BS) void k_primal_q(Args a, int j, int check, unsigned long long* qc,
                                                  unsigned int* qd) {
-  __shared__ long long cur;
-  for (;;) {
-    if (threadIdx.x == 0) cur = (long long)atomicAdd(qc, 1ULL);
+  queue_loop(a.nvt, a.qgrab, qc, [&](int t) {
+    primal_tile(a, t, j, check);
     __syncthreads();
-    const long long t = cur;
-    if (t >= a.nvt) break;
-    primal_tile(a, (int)t, j, check);
-    __syncthreads();
-  }
+  });
   queue_done(qc, qd);
 }
 

@@ -139,7 +139,14 @@ struct Tune {
   double bnec = 0.8;      // ... or by this factor and stopped improving
   double art = 0.2;       // ... or the cycle is this fraction of all iterations
   double pw_theta = 0.5;  // smoothing of the primal-weight update
-  int rule = 1;           // 0: balance weighted primal/dual movement; 1: balance residuals
+  // primal-weight rule at a restart: 0 balance the weighted primal and dual
+  // movement; 1 balance r_bal against max(r_dual, r_gap); 3 balance
+  // max(r_bal, r_soc) against r_gap; 4 balance r_bal against
+  // max(r_dual, min(r_gap, r_bal)).  Rule 1 lets a large gap drive the
+  // weight down while the balance residual stalls (the dual then barely
+  // moves and the gap cannot close: cold solves seen stuck at r_bal ~ 0.2);
+  // rule 4 counts the gap only up to the balance residual.
+  int rule = 4;
   double gain = 0.25;     // exponent of the residual-balancing update
   int arule = 0;          // rule of the adjoint solve (-1: same as rule)
   int flow_rule = 1;      // 1: adapt the flow-class multiplier at restarts
@@ -204,6 +211,7 @@ struct gp_plan {
   int variant = 0;       // 0: one block per tile, 1: persistent work queue
   int ce = 64;           // iterations per graph replay / convergence check
   int qblocks = 2048;    // resident blocks of the work-queue form
+  int qgrab = 4;         // tiles per work-queue counter update
   std::vector<int> tuned_batch;
   double tune_ms[2][3] = {{0}};  // measured ms per iteration [variant][bs 128/256/512]
   DevBuf<unsigned long long> d_qc;  // work-queue counters: dual, primal
@@ -527,15 +535,16 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   HIPCHK(hipMemsetAsync(p->d_y0.p, 0, yoff * sizeof(double), st));
   HIPCHK(hipMemsetAsync(p->d_ybar.p, 0, yoff * sizeof(double), st));
   HIPCHK(hipMemsetAsync(p->d_yhat.p, 0, yoff * sizeof(double), st));
-  p->d_qc.alloc(2);
+  p->d_qc.alloc(2 * kQueueWords);
   p->d_qd.alloc(2);
-  HIPCHK(hipMemsetAsync(p->d_qc.p, 0, 2 * sizeof(unsigned long long), st));
+  HIPCHK(hipMemsetAsync(p->d_qc.p, 0, 2 * kQueueWords * sizeof(unsigned long long), st));
   HIPCHK(hipMemsetAsync(p->d_qd.p, 0, 2 * sizeof(unsigned int), st));
   {
     int dev = 0, ncu = 256;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    p->qblocks = std::max(1, ncu) * 8;
+    p->qblocks = std::max(1, (int)env_or("GP_QBLOCKS_PER_CU", 8.0)) * std::max(1, ncu);
+    p->qgrab = std::max(1, (int)env_or("GP_QGRAB", (double)p->qgrab));
   }
   p->has_solution.assign(p->S, 0);
   p->last_cw.assign(p->S, 0.f);
@@ -554,6 +563,7 @@ Args make_args(gp_plan* p, int adjoint) {
   a.nvt = p->nvt;
   a.nrt = p->nrt;
   a.mode = adjoint;
+  a.qgrab = p->qgrab;
   a.gen_node = p->d_gen_node.p;
   a.gen_cost = p->d_gen_cost.p;
   a.gen_emis = p->d_gen_emis.p;
@@ -682,7 +692,8 @@ void launch_iteration(gp_plan* p, const Args& a, int j, int check, int timed) {
   hipStream_t st = p->stream;
   const int bs = block_size(p);
   HIPCHK(launch_dual(a, bs, j, check, p->max_T, st, timed, p->variant, p->qblocks, p->d_qc.p, p->d_qd.p));
-  HIPCHK(launch_primal(a, bs, j, check, st, timed, p->variant, p->qblocks, p->d_qc.p + 1, p->d_qd.p + 1));
+  HIPCHK(launch_primal(a, bs, j, check, st, timed, p->variant, p->qblocks, p->d_qc.p + kQueueWords,
+                       p->d_qd.p + 1));
 }
 
 // write_check = 0 (tuning only) leaves the stored (xhat, yhat) untouched
@@ -1010,7 +1021,9 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
             cn = std::exp(tn.pw_theta * std::log(dy / dx) + (1.0 - tn.pw_theta) * std::log(c));
         } else {
           const double num = rule == 3 ? std::max(k.r_bal, k.r_soc) : k.r_bal;
-          const double den = rule == 3 ? k.r_gap : std::max(k.r_dual, k.r_gap);
+          const double den = rule == 3   ? k.r_gap
+                             : rule == 4 ? std::max(k.r_dual, std::min(k.r_gap, k.r_bal))
+                                         : std::max(k.r_dual, k.r_gap);
           const double f = std::pow(std::max(num, 1e-16) / std::max(den, 1e-16), tn.gain);
           cn = c * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
         }
@@ -1392,9 +1405,10 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
     HIPCHK(hipEventRecord(ev[0], st));
     for (int j = 0; j < iters; ++j) HIPCHK(launch_dual(a, bs, j, 0, p->max_T, st, 1, v, p->qblocks, qc, qd));
     HIPCHK(hipEventRecord(ev[1], st));
-    HIPCHK(launch_primal(a, bs, 0, 0, st, 1, v, p->qblocks, qc + 1, qd + 1));
+    HIPCHK(launch_primal(a, bs, 0, 0, st, 1, v, p->qblocks, qc + kQueueWords, qd + 1));
     HIPCHK(hipEventRecord(ev[2], st));
-    for (int j = 0; j < iters; ++j) HIPCHK(launch_primal(a, bs, j, 0, st, 1, v, p->qblocks, qc + 1, qd + 1));
+    for (int j = 0; j < iters; ++j)
+      HIPCHK(launch_primal(a, bs, j, 0, st, 1, v, p->qblocks, qc + kQueueWords, qd + 1));
     HIPCHK(hipEventRecord(ev[3], st));
     HIPCHK(hipStreamSynchronize(st));
     float t1 = 0, t2 = 0;

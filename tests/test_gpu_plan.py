@@ -192,3 +192,25 @@ def test_uneven_batch_small():
             ref = case.scenarios[s].weight * Gm.scenario_gradient(qp, sol, 0.0)["grad"] / 4
             gs = g[off[s]:off[s + 1]]
             assert np.linalg.norm(gs - ref) / np.linalg.norm(ref) <= 1e-3
+
+
+def test_cold_solves_along_a_planning_path_converge():
+    """Cold solves at every iterate of a 10-step projected-gradient path on
+    the tiny case converge (a weight rule that lets the duality gap push the
+    primal weight down while the balance residual stalls left several of
+    these stuck at a balance residual of ~0.2)."""
+    cs = cases.config0()
+    eta = cs.eta_min().copy()
+    gamma = cs.gamma()
+    with _plan(cs) as p, _plan(cs) as q:
+        p.solve(eta, [0])
+        g0, _, _ = p.grad([0])
+        alpha = 0.1 * (cs.eta_max() - cs.eta_min()).min() / np.abs(gamma + g0).max()
+        iters = []
+        for k in range(10):
+            eta, phi, delta, rc = p.step(alpha, [0], gamma, eta, warm=1 if k else 0)
+            assert rc == 0
+            _, st, rc = q.solve(eta, [0], warm=0)
+            assert rc == 0, (k, st)
+            iters.append(st[0]["iters"])
+    print(f"\n[gpu] cold iterations along the path: {iters}", flush=True)
