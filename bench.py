@@ -71,10 +71,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload_id):
-    """HBM bytes per launch from committed rocprofv3 counter runs, used only
-    while the kernel source is unchanged since they were taken."""
-    ent = _read_traffic_table().get(f"{kernel}@config{workload_id}")
+def measured_traffic(kernel, block, workload_id):
+    """HBM bytes per launch from committed rocprofv3 counter runs (same
+    kernel, block size and workload), used only while the kernel source is
+    unchanged since they were taken."""
+    ent = _read_traffic_table().get(f"{kernel}<{block}>@config{workload_id}")
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -110,16 +111,18 @@ def cpu_baseline(case, hours=24):
                       f"{dt:.1f} s"}
 
 
-def summarize(stats_csv, fetch_csv, write_csv, pmc_line, workload_id, commands):
+def summarize(stats_csv, pmc_runs, workload_id, commands):
     """Turn rocprofv3 outputs into the short text summaries kept in profiles/:
     per-kernel durations, and HBM bytes per launch of the timed sweep kernels
     from FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by what the same
-    counters read for a 1 GiB fill (writes) and a 1 GiB sum (reads)."""
+    counters read for a 1 GiB fill (writes) and a 1 GiB sum (reads).
+    pmc_runs: [(fetch_csv, write_csv, pmc_line)], one per block size.
+    Returns (summary markdown, traffic table markdown)."""
     import csv
     from collections import defaultdict
 
-    info = json.loads(pmc_line)
-    out = [f"# rocprofv3 summary: {info['pmc_run']}", "", "Commands:", ""]
+    info0 = json.loads(pmc_runs[0][2])
+    out = [f"# rocprofv3 summary: {info0['pmc_run']}", "", "Commands (from /tmp, TMPDIR=/tmp):", ""]
     out += [f"    {c}" for c in commands] + [""]
     out += ["## Kernel durations (--kernel-trace --stats)", "",
             "| kernel | calls | average us | total ms | share |", "|---|---|---|---|---|"]
@@ -127,37 +130,83 @@ def summarize(stats_csv, fetch_csv, write_csv, pmc_line, workload_id, commands):
         for r in csv.DictReader(fh):
             out.append(f"| `{r['Name'][:70]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                        f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f}% |")
-    per = defaultdict(lambda: defaultdict(list))
-    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        with open(path) as fh:
-            for r in csv.DictReader(fh):
-                per[r["Kernel_Name"]][name].append(float(r["Counter_Value"]))
-
-    def avg(kern_prefix, counter):
-        vals = [v for k, d in per.items() if k.startswith(kern_prefix) for v in d[counter]]
-        return sum(vals) / len(vals) if vals else float("nan")
+    out += ["", "## HBM traffic per launch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", ""]
     gib = 1 << 30
-    fill_w = avg("void at::native::vectorized_elementwise_kernel", "WRITE_SIZE") * 1024
-    sum_r = avg("void at::native::reduce_kernel", "FETCH_SIZE") * 1024
-    fw, fr = gib / fill_w, gib / sum_r
-    out += ["", "## HBM traffic per launch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
-            f"Calibration: a 1 GiB fill reads WRITE_SIZE = {fill_w / gib:.4f} GiB (write factor "
-            f"{fw:.4f}); a 1 GiB sum reads FETCH_SIZE = {sum_r / gib:.4f} GiB (read factor {fr:.4f}).", "",
-            "| kernel | FETCH KiB | WRITE KiB | traffic bytes (scaled) | algorithmic bytes |",
-            "|---|---|---|---|---|"]
     rows = []
-    sfx = "_q" if info.get("variant") == 2 else ""
-    for kern, alg in (("k_primal" + sfx, info["primal"]), ("k_dual" + sfx, info["dual"])):
-        pre = f"void gp::{kern}<{info.get('block', 256)}, 1>"
-        f_, w_ = avg(pre, "FETCH_SIZE"), avg(pre, "WRITE_SIZE")
-        traffic = f_ * 1024 * fr + w_ * 1024 * fw
-        out.append(f"| `{pre[8:]}` | {f_:.0f} | {w_:.0f} | {traffic:.0f} | {alg} |")
-        rows.append((kern, traffic))
-    out += ["", "Table read by bench.py (valid while the kernel source hash matches):", "",
-            "| key | bytes_per_launch | source_hash |", "|---|---|---|"]
+    for fetch_csv, write_csv, pmc_line in pmc_runs:
+        info = json.loads(pmc_line)
+        per = defaultdict(lambda: defaultdict(list))
+        for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    per[r["Kernel_Name"]][name].append(float(r["Counter_Value"]))
+
+        def avg(kern_prefix, counter):
+            vals = [v for k, d in per.items() if k.startswith(kern_prefix) for v in d[counter]]
+            return sum(vals) / len(vals) if vals else float("nan")
+        fill_w = avg("void at::native::vectorized_elementwise_kernel", "WRITE_SIZE") * 1024
+        sum_r = avg("void at::native::reduce_kernel", "FETCH_SIZE") * 1024
+        fw, fr = gib / fill_w, gib / sum_r
+        blk = info["block"]
+        out += [f"Block {blk}: calibration 1 GiB fill reads WRITE_SIZE = {fill_w / gib:.4f} GiB (write factor "
+                f"{fw:.4f}); 1 GiB sum reads FETCH_SIZE = {sum_r / gib:.4f} GiB (read factor {fr:.4f}).", "",
+                "| kernel | FETCH KiB | WRITE KiB | traffic bytes (scaled) | algorithmic bytes |",
+                "|---|---|---|---|---|"]
+        sfx = "_q" if info.get("variant") == 2 else ""
+        for kern, alg in (("k_primal" + sfx, info["primal"]), ("k_dual" + sfx, info["dual"])):
+            pre = f"void gp::{kern}<{blk}, 1>"
+            f_, w_ = avg(pre, "FETCH_SIZE"), avg(pre, "WRITE_SIZE")
+            traffic = f_ * 1024 * fr + w_ * 1024 * fw
+            out.append(f"| `{pre[len('void gp::'):]}` | {f_:.0f} | {w_:.0f} | {traffic:.0f} | {alg} |")
+            rows.append((f"{kern}<{blk}>", traffic))
+        out.append("")
     h = kernel_source_hash()
-    out += [f"| {k}@config{workload_id} | {t:.0f} | {h} |" for k, t in rows]
-    return "\n".join(out) + "\n"
+    table = ["# HBM traffic per launch of the sweep kernels", "",
+             f"From the counter runs summarised in `profiles/sweeps_geo240.md`; kernel source hash {h}.",
+             "", "Table read by bench.py (valid while the kernel source hash matches):", "",
+             "| key | bytes_per_launch | source_hash |", "|---|---|---|"]
+    table += [f"| {k}@config{workload_id} | {t:.0f} | {h} |" for k, t in rows]
+    return "\n".join(out) + "\n", "\n".join(table) + "\n"
+
+
+PROFILE_COMMANDS = [
+    "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_c1 -o run -- "
+    "python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu --no-hbm-case",
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch_<B> -o run -- "
+    "python3 <repo>/bench.py --pmc-run --pmc-block <B>      (B = 128, 256, 512)",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write_<B> -o run -- "
+    "python3 <repo>/bench.py --pmc-run --pmc-block <B>",
+    "python bench.py --summarize <out>",
+]
+
+
+def write_profiles(d):
+    runs = []
+    for blk in (128, 256, 512):
+        with open(os.path.join(d, f"pmc_{blk}.out")) as fh:
+            line = next(l for l in fh if l.startswith('{"pmc_run"'))
+        runs.append((os.path.join(d, f"pmc_fetch_{blk}", "run_counter_collection.csv"),
+                     os.path.join(d, f"pmc_write_{blk}", "run_counter_collection.csv"), line))
+    summary, table = summarize(os.path.join(d, "prof_c1", "run_kernel_stats.csv"), runs, 1, PROFILE_COMMANDS)
+    # the bench line of the traced run, beside the profiler's average for the
+    # same (timed) instantiation of the roofline kernel
+    import csv
+    with open(os.path.join(d, "prof_c1.out")) as fh:
+        line = json.loads(next(l for l in fh if l.startswith('{"metric"')))
+    roof = line["roofline"]
+    name = f"void gp::{roof['kernel']}<{roof['launch']['block']}, 1>"
+    with open(os.path.join(d, "prof_c1", "run_kernel_stats.csv")) as fh:
+        prof_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(fh) if r["Name"].startswith(name))
+    summary += ("\n## Roofline kernel: bench.py against the profiler (same run)\n\n"
+                f"bench.py (HIP events, {roof['kernel']}, block {roof['launch']['block']}): "
+                f"{roof['ms_per_launch'] * 1e3:.2f} us per launch, {roof['achieved']} GB/s of algorithmic bytes "
+                f"({roof['bytes_per_launch']} B), {roof['frac'] * 100:.1f} % of 8 TB/s; rocprofv3 average of "
+                f"`{name[len('void gp::'):]}`: {prof_us:.2f} us.  Headline value of that run: "
+                f"{line['value']} {line['unit']}.\n")
+    with open(os.path.join(ROOT, "profiles", "sweeps_geo240.md"), "w") as fh:
+        fh.write(summary)
+    with open(os.path.join(ROOT, "profiles", "traffic.md"), "w") as fh:
+        fh.write(table)
 
 
 def hbm_case_sweeps(iters):
@@ -330,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-hours", type=int, default=24)
     ap.add_argument("--sweep-iters", type=int, default=50)
+    ap.add_argument("--pmc-block", type=int, default=256, choices=[128, 256, 512],
+                    help="block size of the sweeps in --pmc-run")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware counters: one iteration chunk, 10 timed sweeps of "
                          "each kernel and a 1 GiB device copy that calibrates the byte counters")
@@ -343,7 +394,13 @@ def main():
     ap.add_argument("--ws-epochs", type=int, default=150)
     ap.add_argument("--ws-train-prices", type=float, nargs="+", default=[100.0, 175.0, 325.0, 400.0])
     ap.add_argument("--ws-held-price", type=float, default=250.0)
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write profiles/sweeps_geo240.md and profiles/traffic.md from the rocprofv3 outputs "
+                         "under DIR (prof_c1/, pmc_fetch_<block>/, pmc_write_<block>/, pmc_<block>.out)")
     args = ap.parse_args()
+    if args.summarize:
+        write_profiles(args.summarize)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
               "(scenarios would shard across GPUs with one all-reduce of the gradient per step)",
@@ -367,7 +424,8 @@ def main():
     omega = case.omega
     print(f"[bench] {WORKLOADS[args.config]}", file=sys.stderr, flush=True)
     if args.pmc_run:
-        plan = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
+        plan = gridplan.Plan(case, gridplan.options(max_iter=64, block=args.pmc_block, variant=1, check_every=64),
+                             stream=gridplan.current_stream())
         plan.solve(eta, scen, warm=0)
         md, mp = plan.time_sweeps(scen, 10)
         tb, tv, tce, _ = plan.tuning()
@@ -420,7 +478,7 @@ def main():
     achieved = nbytes / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kname, args.config),
+            "traffic": measured_traffic(kname, tb, args.config),
             "bytes_per_launch": nbytes, "ms_per_launch": round(ms, 5),
             "other_kernel_ms": round(md if kname.startswith("k_primal") else mp, 5),
             "launch": {"block": tb, "form": "work queue" if tv == 2 else "tile grid",

@@ -37,9 +37,13 @@ constexpr int kQueueStride = 16;
 constexpr int kQueueWords = kXcd * kQueueStride;
 enum ResetMode { RESET_WARM = 0, RESET_COLD = 1, RESET_PROBE = 2, RESET_RESTORE = 3 };
 
+// a sweep tile whose scenario has T divisible by 4 is processed four hours
+// per thread (16-byte loads of the FP32 state, 32-byte runs of the duals)
+constexpr int32_t kTileVec4 = 0x100;
+
 struct Tile {
   int32_t scen;   // scenario index
-  int32_t cls;    // VarClass or RowClass
+  int32_t cls;    // VarClass or RowClass (sweep tables: | kTileVec4)
   int32_t start;  // first local item (VC_* / RC_BAL / RC_FLOW) or battery index (RC_SOC)
   int32_t count;  // items in this tile (RC_SOC: chains, each its own block)
 };
@@ -85,9 +89,12 @@ struct Args {
   // geometry
   const ScenDev* scen;
   const NetDev* net;
-  const Tile* vtiles;  // variable-sweep tiles
-  const Tile* rtiles;  // row-sweep tiles
+  const Tile* vtiles;  // variable tiles, one item per thread (checks, resets, masks)
+  const Tile* rtiles;  // row tiles, one item per thread
   int32_t nvt, nrt;
+  const Tile* svt;     // tiles of the two sweeps (four hours per thread where
+  const Tile* srt;     // the scenario allows it)
+  int32_t nsvt, nsrt;
   int32_t mode;        // 0 dispatch, 1 adjoint (active entries fixed, free elsewhere)
   int32_t qgrab;       // work-queue form: tiles taken per counter update
   // network data

@@ -97,11 +97,92 @@ __device__ __forceinline__ void dual_update(const Args& a, int64_t row, double s
   if (check) a.yhat[row] = yh;
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+__device__ __forceinline__ void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+// four consecutive doubles (32-byte aligned) as two 16-byte loads
+__device__ __forceinline__ void ldd4(const double* p, double (&v)[4]) {
+  const d2 a0 = reinterpret_cast<const d2*>(p)[0], a1 = reinterpret_cast<const d2*>(p)[1];
+  v[0] = a0.x;
+  v[1] = a0.y;
+  v[2] = a1.x;
+  v[3] = a1.y;
+}
+__device__ __forceinline__ void std4(double* p, const double (&v)[4]) {
+  reinterpret_cast<d2*>(p)[0] = d2{v[0], v[1]};
+  reinterpret_cast<d2*>(p)[1] = d2{v[2], v[3]};
+}
+
+// dual_update on rows [row, row + 4)
+__device__ __forceinline__ void dual_update4(const Args& a, int64_t row, const double (&step)[4], double lam,
+                                             int check) {
+  double yv[4], y0[4], yh[4], e2[4], yn[4];
+  ldd4(a.y + row, yv);
+  ldd4(a.y0 + row, y0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    yh[q] = yv[q] - step[q];
+    e2[q] = 2.0 * yh[q] - yv[q];
+    yn[q] = lam * e2[q] + (1.0 - lam) * y0[q];
+  }
+  std4(a.ybar + row, e2);
+  std4(a.y + row, yn);
+  if (check) std4(a.yhat + row, yh);
+}
+
+// Balance and flow rows, four hours per thread (T divisible by 4, so the
+// four rows share their node or line).
+__device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const ScenDev& sc, const NetDev& nt,
+                                           double c, double lam, int check) {
+  const int li = 4 * (int)threadIdx.x;
+  if (li >= tl.count) return;
+  const int i = tl.start + li;
+  const int T = sc.T;
+  const int64_t TT = T;
+  const float* xs = a.x + sc.xoff;
+  double step[4];
+  if ((tl.cls & 0xff) == RC_BAL) {
+    const int n = i / T, t = i - n * T;
+    f4 res = ld4(xs + (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i);
+    if (!a.mode) res -= ld4(a.load + sc.doff + i);
+    const int e0 = a.term_ptr[nt.tptr_off + n], e1 = a.term_ptr[nt.tptr_off + n + 1];
+    const float* pf = xs + (int64_t)nt.G * TT;
+    const float* pch = xs + (int64_t)(nt.G + nt.L + nt.N) * TT;
+    const float* pdis = pch + (int64_t)nt.B * TT;
+    for (int e = e0; e < e1; ++e) {
+      const int code = a.term[e];
+      const int64_t o = (int64_t)(code >> 2) * TT + t;
+      switch (code & 3) {
+        case TT_GEN: res += ld4(xs + o); break;
+        case TT_BATT: res += ld4(pdis + o) - ld4(pch + o); break;
+        case TT_LINE_TO: res += ld4(pf + o); break;
+        default: res -= ld4(pf + o); break;
+      }
+    }
+    const double f = c * (double)a.sig_bal[nt.node_off + n];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
+    dual_update4(a, sc.yoff + i, step, lam, check);
+  } else {  // RC_FLOW
+    const int l = i / T, t = i - l * T;
+    const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+    const float b = a.line_beta[nt.line_off + l];
+    const float* th = xs + (int64_t)(nt.G + nt.L) * TT;
+    const f4 res = ld4(xs + (int64_t)nt.G * TT + i) - b * (ld4(th + (int64_t)fr * TT + t) - ld4(th + (int64_t)to * TT + t));
+    const double f = c * (double)a.cwf[tl.scen] * (double)a.w.sig_flow;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
+    dual_update4(a, sc.yoff + (int64_t)nt.N * TT + i, step, lam, check);
+  }
+}
+
 // One row tile of the dual sweep.  sres: LDS of at least T floats.  Every
 // thread of the block must call it (the SOC-chain branch synchronises).
 template <int BS>
 __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int check, float* sres) {
-  const Tile tl = a.rtiles[tix];
+  const Tile tl = a.srt[tix];
   const int s = tl.scen;
   if (!a.active[s]) return;
   const ScenDev sc = a.scen[s];
@@ -112,6 +193,10 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
   const int k = a.kbase[s] + j;
   const double lam = (double)(k + 1) / (double)(k + 2);
   const float* xs = a.x + sc.xoff;
+  if (tl.cls & kTileVec4) {
+    dual_rows4(a, tl, sc, nt, c, lam, check);
+    return;
+  }
   if (tl.cls == RC_SOC) {
     // one battery chain per block: residuals to LDS, then the circulant
     // inverse of the chain block (C R^-1 C') applied as a short convolution
@@ -212,11 +297,130 @@ __device__ __forceinline__ double angle_ety(const Args& a, const NetDev& nt, con
   return ey;
 }
 
+// Upd on entries [idx, idx + 4) (same bounds rule per entry)
+__device__ __forceinline__ void upd4(const Upd& u, int64_t idx, const double (&ey)[4], float q, float rho,
+                                     f4 lo, f4 hi) {
+  if (u.mode) {
+    const uchar4 m = *reinterpret_cast<const uchar4*>(u.am + idx);
+    const bool fix[4] = {m.x != 0, m.y != 0, m.z != 0, m.w != 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      lo[k] = fix[k] ? 0.f : -GP_INF;
+      hi[k] = fix[k] ? 0.f : GP_INF;
+    }
+  }
+  const f4 xv = ld4(u.x + idx), x0 = ld4(u.x0 + idx);
+  const float cr = u.c * rho;
+  f4 v, xn;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float g = (float)(ey[k] - (double)q);
+    v[k] = clampf((cr * xv[k] + g) / (u.r + cr), lo[k], hi[k]);
+    xn[k] = u.lam * (2.f * v[k] - xv[k]) + (1.f - u.lam) * x0[k];
+  }
+  st4(u.x + idx, xn);
+  if (u.check) st4(u.xh + idx, v);
+}
+
+// One variable tile, four hours per thread (T divisible by 4).
+__device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, const ScenDev& sc, const NetDev& nt,
+                                             const Upd& u) {
+  const int li = 4 * (int)threadIdx.x;
+  if (li >= tl.count) return;
+  const int i = tl.start + li;
+  const int s = tl.scen;
+  const int T = sc.T;
+  const int64_t TT = T;
+  const double* yb = a.ybar + sc.yoff;
+  const double* yf = yb + (int64_t)nt.N * TT;
+  const double* ys = yf + (int64_t)nt.L * TT;
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  const f4 inf = {GP_INF, GP_INF, GP_INF, GP_INF};
+  double ey[4];
+  switch (tl.cls & 0xff) {
+    case VC_GEN: {
+      const int g = i / T, t = i - g * T;
+      const int n = a.gen_node[nt.gen_off + g];
+      const f4 hi = ld4(a.avail + sc.aoff + i) * a.eta[nt.eta_off + g];
+      const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
+      ldd4(yb + (int64_t)n * TT + t, ey);
+      upd4(u, i, ey, q, a.w.wb, zero, hi);
+      break;
+    }
+    case VC_LINE: {
+      const int l = i / T, t = i - l * T;
+      const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+      double pto[4], pfr[4], mu[4];
+      ldd4(yb + (int64_t)to * TT + t, pto);
+      ldd4(yb + (int64_t)fr * TT + t, pfr);
+      ldd4(yf + i, mu);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ey[k] = pto[k] - pfr[k] + mu[k];
+      const float cap = a.eta[nt.eta_off + nt.G + l];
+      const f4 hi = {cap, cap, cap, cap};
+      upd4(u, (int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + a.cwf[s] * a.w.wf, -hi, hi);
+      break;
+    }
+    case VC_NODE: {
+      const int n = i / T, t = i - n * T;
+      const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ey[k] = 0.0;
+      for (int e = e0; e < e1; ++e) {
+        const int code = a.ang[e];
+        const int l = code >> 1;
+        const double bv = (code & 1) ? -(double)a.line_beta[nt.line_off + l] : (double)a.line_beta[nt.line_off + l];
+        double mu[4];
+        ldd4(yf + (int64_t)l * TT + t, mu);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ey[k] += bv * mu[k];
+      }
+      upd4(u, (int64_t)(nt.G + nt.L) * TT + i, ey, 0.f, a.cwf[s] * a.rho_th[nt.node_off + n], -inf, inf);
+      ldd4(yb + i, ey);
+      upd4(u, (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i, ey, a.mode ? 0.f : a.lambda_u, a.w.wu, zero,
+           inf);
+      break;
+    }
+    default: {  // VC_BATT
+      const int kb = i / T, t = i - kb * T;
+      const int n = a.batt_node[nt.batt_off + kb];
+      double pb[4], nu[4], e[4];
+      ldd4(yb + (int64_t)n * TT + t, pb);
+      ldd4(ys + i, nu);
+      const double nu_next = ys[(int64_t)kb * TT + ((t + 4 == T) ? 0 : t + 4)];
+      const float cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
+      const f4 hic = {cap, cap, cap, cap};
+      const f4 his = hic * a.hours;
+      const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
+      const int64_t BT = (int64_t)nt.B * TT;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = -pb[k] - (double)a.eff * nu[k];
+      upd4(u, base + i, e, 0.f, a.w.rho_b, zero, hic);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = pb[k] + nu[k];
+      upd4(u, base + BT + i, e, 0.f, a.w.rho_b, zero, hic);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) e[k] = nu[k] - (k < 3 ? nu[k + 1] : nu_next);
+      upd4(u, base + 2 * BT + i, e, 0.f, a.w.ws, zero, his);
+      break;
+    }
+  }
+}
+
 // One variable tile of the primal sweep.
 __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int check) {
-  const Tile tl = a.vtiles[tix];
+  const Tile tl = a.svt[tix];
   const int s = tl.scen;
   if (!a.active[s]) return;
+  if (tl.cls & kTileVec4) {
+    const ScenDev sc = a.scen[s];
+    const NetDev nt = a.net[sc.net];
+    const int k = a.kbase[s] + j;
+    Upd u{a.x + sc.xoff, a.x0 + sc.xoff, a.xhat + sc.xoff, a.amask ? a.amask + sc.xoff : nullptr,
+          a.cw[s], (float)(k + 1) / (float)(k + 2), a.r, check, a.mode};
+    primal_tile4(a, tl, sc, nt, u);
+    return;
+  }
   const int li = threadIdx.x;
   if (li >= tl.count) return;
   const int i = tl.start + li;
@@ -281,9 +485,6 @@ __global__ __launch_bounds__(BS) void k_primal(Args a, int j, int check) {
 // persistent work-queue form of the two sweeps
 // ----------------------------------------------------------------------------
 
-// A fixed grid of resident blocks takes tiles from a 64-bit counter until the
-// queue is drained (every block exits once a fetch passes the tile count); the
-// last block to leave resets the counter pair for the next launch.
 // Persistent work queue: one counter per XCD (kQueueStride apart, so each
 // sits on its own cache line), each over the contiguous tile range that the
 // XCD-aware block remap gives that XCD.  A block works its home XCD's range
@@ -332,7 +533,7 @@ template <int BS, int TAG>
 __global__ __launch_bounds__(BS) void k_dual_q(Args a, int j, int check, unsigned long long* qc,
                                                unsigned int* qd) {
   extern __shared__ float sres[];
-  queue_loop(a.nrt, a.qgrab, qc, [&](int t) {
+  queue_loop(a.nsrt, a.qgrab, qc, [&](int t) {
     dual_tile<BS>(a, t, j, check, sres);
     __syncthreads();
   });
@@ -342,7 +543,7 @@ __global__ __launch_bounds__(BS) void k_dual_q(Args a, int j, int check, unsigne
 template <int BS, int TAG>
 __global__ __launch_bounds__(BS) void k_primal_q(Args a, int j, int check, unsigned long long* qc,
                                                  unsigned int* qd) {
-  queue_loop(a.nvt, a.qgrab, qc, [&](int t) {
+  queue_loop(a.nsvt, a.qgrab, qc, [&](int t) {
     primal_tile(a, t, j, check);
     __syncthreads();
   });
@@ -837,7 +1038,7 @@ hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipSt
                        int variant, int qblocks, unsigned long long* qc, unsigned int* qd) {
   const size_t sh = (size_t)max_T * sizeof(float);
   if (variant == 1) {
-    const int g = std::min(qblocks, a.nrt);
+    const int g = std::min(qblocks, a.nsrt);
 #define L_(B)                                                                                   \
   if (timed) hipLaunchKernelGGL((k_dual_q<B, 1>), dim3(g), dim3(B), sh, st, a, j, check, qc, qd); \
   else hipLaunchKernelGGL((k_dual_q<B, 0>), dim3(g), dim3(B), sh, st, a, j, check, qc, qd)
@@ -846,8 +1047,8 @@ hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipSt
     return hipGetLastError();
   }
 #define L_(B)                                                                                     \
-  if (timed) hipLaunchKernelGGL((k_dual<B, 1>), dim3(a.nrt), dim3(B), sh, st, a, j, check);        \
-  else hipLaunchKernelGGL((k_dual<B, 0>), dim3(a.nrt), dim3(B), sh, st, a, j, check)
+  if (timed) hipLaunchKernelGGL((k_dual<B, 1>), dim3(a.nsrt), dim3(B), sh, st, a, j, check);       \
+  else hipLaunchKernelGGL((k_dual<B, 0>), dim3(a.nsrt), dim3(B), sh, st, a, j, check)
   GP_DISPATCH_BS(bs, L_)
 #undef L_
   return hipGetLastError();
@@ -856,7 +1057,7 @@ hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipSt
 hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st, int timed,
                          int variant, int qblocks, unsigned long long* qc, unsigned int* qd) {
   if (variant == 1) {
-    const int g = std::min(qblocks, a.nvt);
+    const int g = std::min(qblocks, a.nsvt);
 #define L_(B)                                                                                    \
   if (timed) hipLaunchKernelGGL((k_primal_q<B, 1>), dim3(g), dim3(B), 0, st, a, j, check, qc, qd); \
   else hipLaunchKernelGGL((k_primal_q<B, 0>), dim3(g), dim3(B), 0, st, a, j, check, qc, qd)
@@ -865,8 +1066,8 @@ hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st
     return hipGetLastError();
   }
 #define L_(B)                                                                                     \
-  if (timed) hipLaunchKernelGGL((k_primal<B, 1>), dim3(a.nvt), dim3(B), 0, st, a, j, check);       \
-  else hipLaunchKernelGGL((k_primal<B, 0>), dim3(a.nvt), dim3(B), 0, st, a, j, check)
+  if (timed) hipLaunchKernelGGL((k_primal<B, 1>), dim3(a.nsvt), dim3(B), 0, st, a, j, check);      \
+  else hipLaunchKernelGGL((k_primal<B, 0>), dim3(a.nsvt), dim3(B), 0, st, a, j, check)
   GP_DISPATCH_BS(bs, L_)
 #undef L_
   return hipGetLastError();

@@ -196,8 +196,10 @@ struct gp_plan {
   PinBuf<int32_t> h_kbase, h_active, h_restart;
   // batch geometry
   std::vector<int> batch;  // scenarios of the current tile tables
-  DevBuf<Tile> d_vt, d_rt;
+  DevBuf<Tile> d_vt, d_rt;     // one item per thread
   int nvt = 0, nrt = 0;
+  DevBuf<Tile> d_svt, d_srt;   // sweep tiles (four hours per thread where T allows)
+  int nsvt = 0, nsrt = 0;
   DevBuf<int32_t> d_ranges, d_bscen;
   DevBuf<double> d_part_v, d_part_r, d_stats;
   PinBuf<double> h_stats;
@@ -426,6 +428,10 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     ScenDev d{};
     d.net = sc.network;
     d.T = sc.T;
+    // every per-scenario block starts on a multiple of 4 entries, so the
+    // sweeps can move four hours at a time with aligned 16-byte accesses
+    avail.resize((avail.size() + 3) / 4 * 4, 0.f);
+    load.resize((load.size() + 3) / 4 * 4, 0.f);
     d.xoff = xoff;
     d.yoff = yoff;
     d.aoff = (int64_t)avail.size();
@@ -484,8 +490,8 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     sh.ny = ny;
     p->scen.push_back(sh);
     p->max_T = std::max(p->max_T, sc.T);
-    xoff += nx;
-    yoff += ny;
+    xoff += (nx + 3) / 4 * 4;
+    yoff += (ny + 3) / 4 * 4;
   }
   p->nx_tot = xoff;
   p->ny_tot = yoff;
@@ -562,6 +568,10 @@ Args make_args(gp_plan* p, int adjoint) {
   a.rtiles = p->d_rt.p;
   a.nvt = p->nvt;
   a.nrt = p->nrt;
+  a.svt = p->d_svt.p;
+  a.srt = p->d_srt.p;
+  a.nsvt = p->nsvt;
+  a.nsrt = p->nsrt;
   a.mode = adjoint;
   a.qgrab = p->qgrab;
   a.gen_node = p->d_gen_node.p;
@@ -632,7 +642,7 @@ void drop_graph(gp_plan* p) {
 void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) {
   if (!force && batch == p->batch && p->nvt > 0) return;
   const int bs = block_size(p);
-  std::vector<Tile> vt, rt;
+  std::vector<Tile> vt, rt, svt, srt;
   std::vector<int32_t> ranges;
   for (int s : batch) {
     const ScenHost& sh = p->scen[s];
@@ -650,6 +660,21 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
     add(rt, RC_BAL, (int64_t)n.N * T);
     add(rt, RC_FLOW, (int64_t)n.L * T);
     for (int k = 0; k < n.B; ++k) rt.push_back(Tile{s, RC_SOC, k, 1});
+    // sweep tables: four hours per thread when T allows it
+    const bool v4 = T % 4 == 0;
+    const int w = v4 ? 4 * bs : bs;
+    const int flag = v4 ? kTileVec4 : 0;
+    auto adds = [&](std::vector<Tile>& dst, int cls, int64_t count) {
+      for (int64_t st = 0; st < count; st += w)
+        dst.push_back(Tile{s, cls | flag, (int32_t)st, (int32_t)std::min<int64_t>(w, count - st)});
+    };
+    adds(svt, VC_GEN, (int64_t)n.G * T);
+    adds(svt, VC_LINE, (int64_t)n.L * T);
+    adds(svt, VC_NODE, (int64_t)n.N * T);
+    adds(svt, VC_BATT, (int64_t)n.B * T);
+    adds(srt, RC_BAL, (int64_t)n.N * T);
+    adds(srt, RC_FLOW, (int64_t)n.L * T);
+    for (int k = 0; k < n.B; ++k) srt.push_back(Tile{s, RC_SOC, k, 1});
     ranges.push_back(v0);
     ranges.push_back((int)vt.size());
     ranges.push_back(r0);
@@ -662,6 +687,10 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
   p->d_rt.upload(rt, st);
   p->nvt = (int)vt.size();
   p->nrt = (int)rt.size();
+  p->d_svt.upload(svt, st);
+  p->d_srt.upload(srt, st);
+  p->nsvt = (int)svt.size();
+  p->nsrt = (int)srt.size();
   p->d_ranges.upload(ranges, st);
   std::vector<int32_t> bs_(batch.begin(), batch.end());
   p->d_bscen.upload(bs_, st);
