@@ -209,6 +209,63 @@ def write_profiles(d):
         fh.write(table)
 
 
+def write_mlp_profile(d):
+    """profiles/mlp_forward_geo1000.md from <d>/prof_mlp (kernel trace of
+    `bench.py --mlp`) and that run's JSON line."""
+    import csv
+    with open(os.path.join(d, "prof_mlp.out")) as fh:
+        line = json.loads(next(l for l in fh if l.startswith('{"metric"')))
+    roof = line["roofline"]
+    out = ["# rocprofv3 summary: warm-start network forward, " + line["config"]["workload"], "",
+           "Command (from /tmp, TMPDIR=/tmp):", "",
+           "    rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_mlp -o run -- "
+           "python3 <repo>/bench.py --mlp", "",
+           "| kernel | calls | average us | total ms |", "|---|---|---|---|"]
+    gemm_ns, gemm_calls = 0.0, 0
+    with open(os.path.join(d, "prof_mlp", "run_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            out.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+            if "k_gemm" in r["Name"]:
+                gemm_ns += float(r["TotalDurationNs"])
+                gemm_calls += int(r["Calls"])
+    fwd = gemm_calls // 4
+    out += ["", f"bench.py (HIP events): {roof['ms_per_forward'] * 1e3:.1f} us per forward over {roof['rows']} rows, "
+            f"{roof['flops_per_forward'] / 1e9:.1f} GFLOP, {roof['achieved']} TFLOP/s = "
+            f"{roof['frac'] * 100:.2f} % of the 2.5 PFLOP/s dense BF16 peak.",
+            f"rocprofv3: {gemm_calls} GEMM launches = {fwd} forwards of 4 layers (one set-up call, one untimed, "
+            f"the timed ones); GEMM time per forward {gemm_ns / max(fwd, 1) / 1e3:.1f} us."]
+    with open(os.path.join(ROOT, "profiles", "mlp_forward_geo1000.md"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
+def write_warmstart_profile(d):
+    """profiles/warmstart_geo1000.md from <d>/ws_bench.json (the JSON line of
+    `bench.py --warm-start`) and its per-step log."""
+    with open(os.path.join(d, "ws_bench.json")) as fh:
+        r = json.loads(next(l for l in fh if l.startswith('{"metric"')))
+    out = ["# s/gradient step on the 1000-node workload: cold vs learned warm vs previous-iterate warm", "",
+           "Command:", "", "    python bench.py --warm-start", "",
+           f"Workload: {r['config']['workload']}; tolerance {r['config']['tol']}; step size {r['config']['alpha']:.4g}.",
+           "", "| arm | median s/step | s per step | max iterations per step | starts (0 cold, 1 warm, 2 screened, "
+           "3 stalled) |", "|---|---|---|---|---|"]
+    for arm in ("cold", "previous", "learned"):
+        a = r["arms"][arm]
+        out.append(f"| {arm} | {a['s_per_step_median']} | {a['s_per_step']} | {a['iterations_max_per_step']} | "
+                   f"{a['starts']} |")
+    t = r["training"]
+    out += ["", f"Speedup (median s/step) cold / learned: {r['speedup_cold_over_learned']}; cold / previous-iterate: "
+            f"{r['speedup_cold_over_previous']}.  Largest capacity difference between the learned and the cold run "
+            f"after {r['steps']} steps: {r['max_eta_difference_learned_vs_cold_MW']:.3g} MW.", "",
+            f"Training: planning runs under storage costs {t['storage_costs']} $/kWh, {t['steps_per_run']} steps each, "
+            f"{t['rows']} rows, {t['epochs']} epochs of Adam in {t['train_s']} s (collection {t['collect_s']} s); "
+            f"loss (standardised units) {t['loss_first']:.4f} -> {t['loss_last']:.4f}; network {t['network']}.", "",
+            f"Network forward on {r['roofline']['rows']} rows: {r['roofline']['achieved']} TFLOP/s "
+            f"({r['roofline']['frac'] * 100:.2f} % of the dense BF16 peak)."]
+    with open(os.path.join(ROOT, "profiles", "warmstart_geo1000.md"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
 def hbm_case_sweeps(iters):
     """The sweep kernels on a working set far above the 256 MB Infinity
     Cache: 16 scenarios of the 1000-node workload (a GPU's share of its 128),
@@ -231,6 +288,43 @@ def hbm_case_sweeps(iters):
         res[k] = {"ms_per_launch": round(ms, 5), "bytes_per_launch": nb, "achieved_GBs": round(gbs, 1),
                   "frac": round(gbs / HBM_PEAK_GBS, 4)}
     return res
+
+
+def mlp_roofline(plan, case, net, iters=20):
+    """MFMA roofline of the warm-start network's forward pass on the rows of
+    every scenario of the workload (one row per scenario and node), input
+    features built on the device at eta_min.  Returns the roofline object."""
+    import torch
+
+    scen = list(range(len(case.scenarios)))
+    rows, T = plan.nn_rows(scen)
+    X = torch.empty((rows, 5 * T + 3), dtype=torch.float32, device="cuda")
+    plan.features(case.eta_min(), scen, X)
+    net.forward(X)
+    ms = net.time_forward(rows, iters)
+    flops = net.flops_per_row() * rows
+    tflops = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": "k_gemm (network forward: 4 GEMMs with bias/ReLU epilogues)",
+            "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tflops / 2500.0, 5),
+            "traffic": None, "rows": rows, "flops_per_forward": flops, "ms_per_forward": round(ms, 5),
+            "dtype": "bf16 x bf16 -> f32"}
+
+
+def mlp_leg(args):
+    """The warm-start network's forward pass alone (random weights), for its
+    roofline and a profiler trace: 128 scenarios x 1000 nodes = 128,000 rows."""
+    from paper_2410_13055_amd import cases, gridplan
+
+    case = cases.config4()
+    plan = gridplan.Plan(case, gridplan.options(), stream=gridplan.current_stream())
+    T = case.scenarios[0].T
+    net = gridplan.MLP(5 * T + 3, 512, 3, 2 * T, seed=0, stream=gridplan.current_stream())
+    roof = mlp_roofline(plan, case, net, args.sweep_iters)
+    print(json.dumps({"metric": "warm-start network forward, TFLOP/s", "value": roof["achieved"],
+                      "unit": "TFLOP/s", "config": {"workload": WORKLOADS[4] + "; one row per scenario and node"},
+                      "roofline": roof}), flush=True)
+    net.close()
+    plan.close()
 
 
 def warm_start_leg(args):
@@ -321,13 +415,9 @@ def warm_start_leg(args):
         arms[arm] = run(p, held_price, 999, arm)
         if p is not plan:
             p.close()
-    # inference GEMMs: MFMA roofline of the network's forward pass
-    rows = B * N
-    X = ws.features(lo, pool[:B])
-    ws.net.forward(X)
-    ms = ws.net.time_forward(rows, 20)
-    flops = ws.net.flops_per_row() * rows
-    tflops = flops / (ms * 1e-3) / 1e12
+    # inference GEMMs: MFMA roofline of the trained network's forward pass
+    # on the rows of all 128 scenarios
+    roof = mlp_roofline(plan, case, ws.net)
     plan.close()
 
     def summary(a):
@@ -362,10 +452,7 @@ def warm_start_leg(args):
                      "epochs": args.ws_epochs, "loss_first": losses[0], "loss_last": losses[-1],
                      "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
                      "network": f"{5 * T + 3} -> 512 x3 -> {2 * T}, {ws.net.n_params} parameters"},
-        "roofline": {"bound": "mfma", "kernel": "k_gemm (network forward, 4 layers)",
-                     "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": round(tflops / 2500.0, 5), "traffic": None, "rows": rows,
-                     "ms_per_forward": round(ms, 5)},
+        "roofline": roof,
     }
     print(json.dumps(out), flush=True)
 
@@ -386,6 +473,8 @@ def main():
                          "each kernel and a 1 GiB device copy that calibrates the byte counters")
     ap.add_argument("--no-hbm-case", dest="hbm_case", action="store_false",
                     help="skip timing the sweeps on 16 scenarios of the 1000-node workload")
+    ap.add_argument("--mlp", action="store_true",
+                    help="time the warm-start network's forward pass on 128,000 rows (its MFMA roofline)")
     ap.add_argument("--warm-start", action="store_true",
                     help="s/gradient step on the 1000-node workload: cold vs learned warm vs previous-iterate")
     ap.add_argument("--ws-pool", type=int, default=16)
@@ -399,7 +488,12 @@ def main():
                          "under DIR (prof_c1/, pmc_fetch_<block>/, pmc_write_<block>/, pmc_<block>.out)")
     args = ap.parse_args()
     if args.summarize:
-        write_profiles(args.summarize)
+        if os.path.exists(os.path.join(args.summarize, "prof_c1")):
+            write_profiles(args.summarize)
+        if os.path.exists(os.path.join(args.summarize, "prof_mlp")):
+            write_mlp_profile(args.summarize)
+        if os.path.exists(os.path.join(args.summarize, "ws_bench.json")):
+            write_warmstart_profile(args.summarize)
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
@@ -416,6 +510,9 @@ def main():
     torch.cuda.set_device(0)
     if args.warm_start:
         warm_start_leg(args)
+        return
+    if args.mlp:
+        mlp_leg(args)
         return
     case = cases.by_id(args.config)
     scen = list(range(len(case.scenarios)))

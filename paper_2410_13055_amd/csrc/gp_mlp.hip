@@ -32,82 +32,135 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int LDA = BK + 8;  // LDS row pitch (bf16) to spread banks
+constexpr int BN = 128, BK = 64;
+constexpr int LDA = BK + 8;  // LDS row pitch (bf16): 144 bytes, keeps 16-byte alignment
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
 
 enum Epi { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2 };
 
-// C = op(A) op(B) (+ bias, relu).  A: TA ? [K x M] : [M x K]; B: TB ? [N x K] :
-// [K x N].  Outputs: Cf (FP32, nullable) and/or Cb (BF16, nullable), both
-// [M x N] row-major with leading dimension N.  accumulate: Cf += result.
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, const __bf16* __restrict__ B,
-                                              float* __restrict__ Cf, __bf16* __restrict__ Cb,
-                                              const float* __restrict__ bias, int M, int N, int K, int epi,
-                                              int accumulate) {
-  __shared__ __bf16 As[BM * LDA];  // [m][k]
-  __shared__ __bf16 Bs[BN * LDA];  // [n][k]
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  f32x16 acc[2][2];
+struct GemmArgs {
+  const __bf16* A;
+  const __bf16* B;
+  float* Cf;         // FP32 output [M x N] (nullable)
+  __bf16* Cb;        // BF16 output [M x N] (nullable)
+  const float* bias;
+  int M, N, K;       // C = op(A) op(B), k in [0, K)
+  int lda, ldb;      // row strides of A and B as stored
+  int Ka, Kb;        // entries of A / B with k >= Ka / Kb read as zero
+  int epi, accumulate;
+  int vecA, vecB;    // 1: stage 8 contiguous elements per 16-byte load
+};
+
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// one 8-element chunk of a staged operand: 8 bf16 in registers
+struct Chunk {
+  u16x8 v;
+};
+
+__device__ __forceinline__ unsigned short bits(__bf16 x) { return __builtin_bit_cast(unsigned short, x); }
+__device__ __forceinline__ __bf16 frombits(unsigned short u) { return __builtin_bit_cast(__bf16, u); }
+
+// Operand tiles in LDS are [row][k] (row = m for A, n for B), BK k per
+// row.  A tile of R rows has R*BK/8 chunks of 8 k; thread t stages chunks
+// t, t + 256, ...  For a "k-contiguous" operand (A not transposed, B
+// transposed) a chunk is 8 consecutive k of one row; otherwise it is 8
+// consecutive rows at one k (stored transposed into LDS).
+template <int R, bool KCONT>
+__device__ __forceinline__ void load_chunks(const __bf16* __restrict__ P, int ld, int row0, int nrows, int k0,
+                                            int kvalid, bool vec, Chunk (&c)[R * BK / 8 / 256]) {
+  constexpr int NC = R * BK / 8 / 256;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int q = 0; q < NC; ++q) {
+    const int e = (int)threadIdx.x + 256 * q;
+    if (KCONT) {
+      const int r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
+      const int gr = row0 + r, gk = k0 + kq;
+      if (vec) {
+        if (gr < nrows && gk < kvalid) c[q].v = *reinterpret_cast<const u16x8*>(P + (int64_t)gr * ld + gk);
+        else c[q].v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          c[q].v[i] = (gr < nrows && gk + i < kvalid) ? bits(P[(int64_t)gr * ld + gk + i]) : (unsigned short)0;
+      }
+    } else {
+      const int k = e / (R / 8), rq = (e % (R / 8)) * 8;
+      const int gr = row0 + rq, gk = k0 + k;
+      if (vec) {
+        if (gr < nrows && gk < kvalid) c[q].v = *reinterpret_cast<const u16x8*>(P + (int64_t)gk * ld + gr);
+        else c[q].v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          c[q].v[i] = (gr + i < nrows && gk < kvalid) ? bits(P[(int64_t)gk * ld + gr + i]) : (unsigned short)0;
+      }
+    }
+  }
+}
+
+template <int R, bool KCONT>
+__device__ __forceinline__ void store_chunks(__bf16* __restrict__ S, const Chunk (&c)[R * BK / 8 / 256]) {
+  constexpr int NC = R * BK / 8 / 256;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const int e = (int)threadIdx.x + 256 * q;
+    if (KCONT) {
+      const int r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
+      *reinterpret_cast<u16x8*>(S + r * LDA + kq) = c[q].v;
+    } else {
+      const int k = e / (R / 8), rq = (e % (R / 8)) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[(rq + i) * LDA + k] = frombits(c[q].v[i]);
+    }
+  }
+}
+
+// C = op(A) op(B) (+ bias, relu), BF16 operands, FP32 accumulation on the
+// 32x32x16 MFMA.  Block tile BM x 128 x 64 with 4 wavefronts in 2 x 2, each
+// owning (BM/2) x 64 of C; the next K tile is fetched into registers while
+// the current one is multiplied.
+template <int BM, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  static_assert(BM == 64 || BM == 128, "BM");
+  constexpr int MI = BM / 64;  // 32-row MFMA tiles per wave along m
+  __shared__ __attribute__((aligned(16))) __bf16 As[BM * LDA];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN * LDA];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * 64;
+  f32x16 acc[MI][2];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // stage A tile: BM x BK elements, 16 per thread
-    for (int e = tid; e < BM * BK; e += 256) {
-      int mm, kk;
-      if (!TA) {
-        mm = e / BK;
-        kk = e % BK;
-      } else {
-        kk = e / BM;
-        mm = e % BM;
-      }
-      const int gm = m0 + mm, gk = k0 + kk;
-      __bf16 v = to_bf16(0.f);
-      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
-      As[mm * LDA + kk] = v;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int nn, kk;
-      if (TB) {
-        nn = e / BK;
-        kk = e % BK;
-      } else {
-        kk = e / BN;
-        nn = e % BN;
-      }
-      const int gn = n0 + nn, gk = k0 + kk;
-      __bf16 v = to_bf16(0.f);
-      if (gn < N && gk < K) v = TB ? B[(int64_t)gn * K + gk] : B[(int64_t)gk * N + gn];
-      Bs[nn * LDA + kk] = v;
-    }
+  Chunk ca[BM * BK / 8 / 256], cb[BN * BK / 8 / 256];
+  load_chunks<BM, !TA>(g.A, g.lda, m0, g.M, 0, g.Ka, g.vecA, ca);
+  load_chunks<BN, TB>(g.B, g.ldb, n0, g.N, 0, g.Kb, g.vecB, cb);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    store_chunks<BM, !TA>(As, ca);
+    store_chunks<BN, TB>(Bs, cb);
     __syncthreads();
+    if (k0 + BK < g.K) {  // prefetch the next K tile while this one is used
+      load_chunks<BM, !TA>(g.A, g.lda, m0, g.M, k0 + BK, g.Ka, g.vecA, ca);
+      load_chunks<BN, TB>(g.B, g.ldb, n0, g.N, k0 + BK, g.Kb, g.vecB, cb);
+    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 16) {
       const int kq = ks + 8 * (lane >> 5);
-      bf16x8 af[2], bfr[2];
+      bf16x8 af[MI], bfr[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const __bf16* pa = &As[(wm + 32 * i + (lane & 31)) * LDA + kq];
-        const __bf16* pb = &Bs[(wn + 32 * i + (lane & 31)) * LDA + kq];
+      for (int i = 0; i < MI; ++i)
+        af[i] = *reinterpret_cast<const bf16x8*>(&As[(wm + 32 * i + (lane & 31)) * LDA + kq]);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          af[i][q] = pa[q];
-          bfr[i][q] = pb[q];
-        }
-      }
+      for (int j = 0; j < 2; ++j)
+        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn + 32 * j + (lane & 31)) * LDA + kq]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
@@ -116,22 +169,30 @@ __global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A, cons
   }
   // epilogue
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int col = n0 + wn + 32 * j + (lane & 31);
-        if (row < M && col < N) {
+        if (row < g.M && col < g.N) {
           float r = acc[i][j][v];
-          if (epi != EPI_NONE) r += bias[col];
-          if (epi == EPI_BIAS_RELU) r = fmaxf(r, 0.f);
-          const int64_t o = (int64_t)row * N + col;
-          if (Cf) Cf[o] = accumulate ? Cf[o] + r : r;
-          if (Cb) Cb[o] = to_bf16(r);
+          if (g.epi != EPI_NONE) r += g.bias[col];
+          if (g.epi == EPI_BIAS_RELU) r = fmaxf(r, 0.f);
+          const int64_t o = (int64_t)row * g.N + col;
+          if (g.Cf) g.Cf[o] = g.accumulate ? g.Cf[o] + r : r;
+          if (g.Cb) g.Cb[o] = to_bf16(r);
         }
       }
+}
+
+// Wt [N x ldt] = bf16(W [K x N])^T, zero in columns K..ldt-1
+__global__ void k_transpose_bf16(const float* __restrict__ W, __bf16* __restrict__ Wt, int K, int N, int ldt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)N * ldt) return;
+  const int n = (int)(i / ldt), k = (int)(i - (int64_t)n * ldt);
+  Wt[i] = to_bf16(k < K ? W[(int64_t)k * N + n] : 0.f);
 }
 
 __global__ void k_cast_bf16(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n) {
@@ -139,13 +200,20 @@ __global__ void k_cast_bf16(const float* __restrict__ x, __bf16* __restrict__ y,
   if (i < n) y[i] = to_bf16(x[i]);
 }
 
-// input standardisation fused into the cast: y = bf16((x - mu[c]) * isd[c])
-__global__ void k_cast_std(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n, int ncol,
-                           const float* __restrict__ mu, const float* __restrict__ isd) {
+// network input: Y [rows x npad] = bf16((X - mu[c]) * isd[c]) for c < ncol
+// (no standardisation when mu is null), zero in the padding columns
+__global__ void k_cast_input(const float* __restrict__ x, __bf16* __restrict__ y, int64_t rows, int ncol, int npad,
+                             const float* __restrict__ mu, const float* __restrict__ isd) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = (int)(i % ncol);
-  y[i] = to_bf16((x[i] - mu[c]) * isd[c]);
+  if (i >= rows * npad) return;
+  const int64_t r = i / npad;
+  const int c = (int)(i - r * npad);
+  float v = 0.f;
+  if (c < ncol) {
+    v = x[r * ncol + c];
+    if (mu) v = (v - mu[c]) * isd[c];
+  }
+  y[i] = to_bf16(v);
 }
 
 // network output back in target units: Y = Z * sd[c] + mu[c]
@@ -300,13 +368,31 @@ struct Buf {
   }
 };
 
-void launch_gemm(bool ta, bool tb, const __bf16* A, const __bf16* B, float* Cf, __bf16* Cb, const float* bias,
-                 int M, int N, int K, int epi, int accumulate, hipStream_t st) {
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
-  else if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
-  else if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
-  else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, A, B, Cf, Cb, bias, M, N, K, epi, accumulate);
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// C [M x N] = op(A) op(B).  A: ta ? [K x M] (stride lda) : [M x K] (stride
+// lda); B: tb ? [N x K] : [K x N] (stride ldb).  Entries at k >= Ka of A and
+// k >= Kb of B are read as zero (padding columns of A may hold anything
+// finite only if Kb bounds them).
+void launch_gemm(bool ta, bool tb, const __bf16* A, int lda, int Ka, const __bf16* B, int ldb, int Kb, float* Cf,
+                 __bf16* Cb, const float* bias, int M, int N, int K, int epi, int accumulate, hipStream_t st) {
+  GemmArgs g{A, B, Cf, Cb, bias, M, N, K, lda, ldb, Ka, Kb, epi, accumulate, 0, 0};
+  // 16-byte staging needs every chunk to start on a multiple of 8 elements
+  // of an aligned base and to lie wholly inside or outside the valid range
+  g.vecA = aligned16(A) && lda % 8 == 0 && (ta ? M % 8 == 0 : Ka % 8 == 0);
+  g.vecB = aligned16(B) && ldb % 8 == 0 && (tb ? Kb % 8 == 0 : N % 8 == 0);
+  const int gn = (N + BN - 1) / BN;
+  const bool small = (int64_t)gn * ((M + 127) / 128) < 512;  // fill the CUs with 64-row tiles
+#define GEMM_(BMv)                                                                                 \
+  {                                                                                                \
+    dim3 grid(gn, (M + BMv - 1) / BMv);                                                            \
+    if (!ta && !tb) hipLaunchKernelGGL((k_gemm<BMv, false, false>), grid, dim3(256), 0, st, g);     \
+    else if (!ta && tb) hipLaunchKernelGGL((k_gemm<BMv, false, true>), grid, dim3(256), 0, st, g);  \
+    else if (ta && !tb) hipLaunchKernelGGL((k_gemm<BMv, true, false>), grid, dim3(256), 0, st, g);  \
+    else hipLaunchKernelGGL((k_gemm<BMv, true, true>), grid, dim3(256), 0, st, g);                  \
+  }
+  if (small) GEMM_(64) else GEMM_(128)
+#undef GEMM_
   MCHK(hipGetLastError());
 }
 
@@ -320,14 +406,20 @@ struct gp_mlp {
   std::string err;
   std::vector<int> dims;  // n_in, width..., n_out
   int L = 0;              // number of linear layers
+  int n_pad = 0;          // input row stride: n_in rounded up to 8 (zero columns)
   std::vector<int64_t> woff, boff;  // offsets into the flat parameter vector
   int64_t nparam = 0;
   Buf<float> w, g, m, v;  // FP32 masters, gradients, Adam moments
   Buf<__bf16> wb;         // BF16 copy (weights only; biases stay FP32)
+  // BF16 transposed copy for the forward pass: layer l as [out x in_l]
+  // (row stride n_pad for layer 0, zero padding), so both forward operands
+  // are staged k-contiguous with 16-byte loads and stores
+  Buf<__bf16> wbt;
+  std::vector<int64_t> wtoff;
   int64_t step = 0;
   // activations for a batch
   int64_t cap_rows = 0;
-  std::vector<Buf<__bf16>> act;  // act[l]: input of layer l, [rows x dims[l]] BF16
+  std::vector<Buf<__bf16>> act;  // act[l]: input of layer l, [rows x width_l] BF16 (layer 0: n_pad)
   Buf<float> out, dy;            // [rows x n_out] FP32
   Buf<float> gf;                 // FP32 gradient wrt a hidden activation (largest width)
   Buf<__bf16> gb0, gb1;          // BF16 gradients (ping-pong)
@@ -350,7 +442,7 @@ thread_local std::string g_mlp_init_error;
 void ensure_rows(gp_mlp* m, int64_t rows) {
   if (rows <= m->cap_rows) return;
   m->act.resize(m->L);
-  for (int l = 0; l < m->L; ++l) m->act[l].alloc((size_t)rows * m->dims[l]);
+  for (int l = 0; l < m->L; ++l) m->act[l].alloc((size_t)rows * (l == 0 ? m->n_pad : m->dims[l]));
   const int nout = m->dims.back();
   m->out.alloc((size_t)rows * nout);
   m->dy.alloc((size_t)rows * nout);
@@ -363,17 +455,29 @@ void ensure_rows(gp_mlp* m, int64_t rows) {
   m->cap_rows = rows;
 }
 
+// refresh the transposed BF16 weights from the FP32 masters
+void refresh_wt(gp_mlp* m) {
+  for (int l = 0; l < m->L; ++l) {
+    const int K = m->dims[l], N = m->dims[l + 1], ldt = l == 0 ? m->n_pad : K;
+    hipLaunchKernelGGL(k_transpose_bf16, dim3(nblk((int64_t)N * ldt)), dim3(256), 0, m->stream, m->w.p + m->woff[l],
+                       m->wbt.p + m->wtoff[l], K, N, ldt);
+  }
+  MCHK(hipGetLastError());
+}
+
 // forward over `rows` rows whose BF16 input is already in act[0]
 void forward(gp_mlp* m, int64_t rows) {
   hipStream_t st = m->stream;
   for (int l = 0; l < m->L; ++l) {
-    const int K = m->dims[l], N = m->dims[l + 1];
-    const __bf16* W = m->wb.p + m->woff[l];
+    const int N = m->dims[l + 1];
+    const int K = l == 0 ? m->n_pad : m->dims[l];  // layer 0: the zero-padded input
+    const __bf16* Wt = m->wbt.p + m->wtoff[l];
     const float* b = m->w.p + m->boff[l];
     if (l + 1 < m->L)
-      launch_gemm(false, false, m->act[l].p, W, nullptr, m->act[l + 1].p, b, (int)rows, N, K, EPI_BIAS_RELU, 0, st);
+      launch_gemm(false, true, m->act[l].p, K, K, Wt, K, K, nullptr, m->act[l + 1].p, b, (int)rows, N, K,
+                  EPI_BIAS_RELU, 0, st);
     else
-      launch_gemm(false, false, m->act[l].p, W, m->out.p, nullptr, b, (int)rows, N, K, EPI_BIAS, 0, st);
+      launch_gemm(false, true, m->act[l].p, K, K, Wt, K, K, m->out.p, nullptr, b, (int)rows, N, K, EPI_BIAS, 0, st);
   }
 }
 
@@ -386,11 +490,8 @@ void load_input(gp_mlp* m, const float* X, int64_t rows, int on_device) {
     MCHK(hipMemcpyAsync(tmp.p, X, n * sizeof(float), hipMemcpyHostToDevice, m->stream));
     src = tmp.p;
   }
-  if (m->scaled)
-    hipLaunchKernelGGL(k_cast_std, dim3(nblk(n)), dim3(256), 0, m->stream, src, m->act[0].p, n, m->dims[0],
-                       m->xmu.p, m->xisd.p);
-  else
-    hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(n)), dim3(256), 0, m->stream, src, m->act[0].p, n);
+  hipLaunchKernelGGL(k_cast_input, dim3(nblk(rows * m->n_pad)), dim3(256), 0, m->stream, src, m->act[0].p, rows,
+                     m->dims[0], m->n_pad, m->scaled ? m->xmu.p : nullptr, m->scaled ? m->xisd.p : nullptr);
   MCHK(hipGetLastError());
   if (!on_device) MCHK(hipStreamSynchronize(m->stream));
   m->loaded_rows = rows;
@@ -418,15 +519,16 @@ double loss_backward(gp_mlp* m, const float* Tgt, int64_t rows, int on_device) {
   __bf16* gnext_b = m->gb1.p;
   for (int l = m->L - 1; l >= 0; --l) {
     const int K = m->dims[l], N = m->dims[l + 1];
-    // dW_l = act_l^T g  [K x N]
-    launch_gemm(true, false, m->act[l].p, gcur_b, m->g.p + m->woff[l], nullptr, nullptr, K, N, (int)rows, EPI_NONE,
-                0, st);
+    const int lda = l == 0 ? m->n_pad : K;
+    // dW_l = act_l^T g  [K x N] (a sum over the rows)
+    launch_gemm(true, false, m->act[l].p, lda, (int)rows, gcur_b, N, (int)rows, m->g.p + m->woff[l], nullptr,
+                nullptr, K, N, (int)rows, EPI_NONE, 0, st);
     hipLaunchKernelGGL(k_colsum, dim3(nblk(N)), dim3(256), 0, st, gcur_f, m->g.p + m->boff[l], (int)rows, N);
     MCHK(hipGetLastError());
     if (l > 0) {
       // g_prev = g W_l^T, then through the ReLU of layer l-1's output (act_l)
-      launch_gemm(false, true, gcur_b, m->wb.p + m->woff[l], m->gf.p, nullptr, nullptr, (int)rows, K, N, EPI_NONE,
-                  0, st);
+      launch_gemm(false, true, gcur_b, N, N, m->wb.p + m->woff[l], N, N, m->gf.p, nullptr, nullptr, (int)rows, K, N,
+                  EPI_NONE, 0, st);
       const int64_t nk = rows * K;
       hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(nk)), dim3(256), 0, st, m->gf.p, m->act[l].p, gnext_b, nk);
       MCHK(hipGetLastError());
@@ -506,6 +608,7 @@ int mlp_init(gp_mlp** out, int32_t n_in, int32_t width, int32_t hidden_layers, i
     for (int l = 0; l < hidden_layers; ++l) m->dims.push_back(width);
     m->dims.push_back(n_out);
     m->L = (int)m->dims.size() - 1;
+    m->n_pad = (n_in + 7) / 8 * 8;
     int64_t o = 0;
     for (int l = 0; l < m->L; ++l) {
       m->woff.push_back(o);
@@ -529,11 +632,18 @@ int mlp_init(gp_mlp** out, int32_t n_in, int32_t width, int32_t hidden_layers, i
     m->m.alloc(o);
     m->v.alloc(o);
     m->wb.alloc(o);
+    int64_t ot = 0;
+    for (int l = 0; l < m->L; ++l) {
+      m->wtoff.push_back(ot);
+      ot += (int64_t)m->dims[l + 1] * (l == 0 ? m->n_pad : m->dims[l]);
+    }
+    m->wbt.alloc(ot);
     MCHK(hipMemcpyAsync(m->w.p, w.data(), o * sizeof(float), hipMemcpyHostToDevice, m->stream));
     MCHK(hipMemsetAsync(m->m.p, 0, o * sizeof(float), m->stream));
     MCHK(hipMemsetAsync(m->v.p, 0, o * sizeof(float), m->stream));
     MCHK(hipMemsetAsync(m->g.p, 0, o * sizeof(float), m->stream));
     hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(o)), dim3(256), 0, m->stream, m->w.p, m->wb.p, o);
+    refresh_wt(m);
     MCHK(hipGetLastError());
     MCHK(hipStreamSynchronize(m->stream));
   } catch (const MlpError& e) {
@@ -569,6 +679,7 @@ int mlp_set_params(gp_mlp* m, const float* w_in) {
       if (!std::isfinite(w_in[i])) mfail(GP_EINVAL, "parameter %lld is not finite", (long long)i);
     MCHK(hipMemcpyAsync(m->w.p, w_in, m->nparam * sizeof(float), hipMemcpyHostToDevice, m->stream));
     hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(m->nparam)), dim3(256), 0, m->stream, m->w.p, m->wb.p, m->nparam);
+    refresh_wt(m);
     MCHK(hipGetLastError());
     MCHK(hipStreamSynchronize(m->stream));
     return GP_OK;
@@ -640,6 +751,7 @@ int mlp_adam_step(gp_mlp* m, const float* X, const float* T, int64_t rows, int32
     hipLaunchKernelGGL(k_adam, dim3(nblk(nbias)), dim3(256), 0, m->stream, m->w.p + nw, m->g.p + nw, m->m.p + nw,
                        m->v.p + nw, (__bf16*)nullptr, nbias, (float)lr, b1, b2, 1e-8f, c1, c2);
     MCHK(hipGetLastError());
+    refresh_wt(m);
     MCHK(hipStreamSynchronize(m->stream));
     return GP_OK;
   });
@@ -755,7 +867,8 @@ int mlp_gemm_test(const float* A, const float* B, float* C, int32_t M, int32_t N
     MCHK(hipMemcpy(fb.p, B, nb * sizeof(float), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(na)), dim3(256), 0, st, fa.p, ba.p, na);
     hipLaunchKernelGGL(k_cast_bf16, dim3(nblk(nb)), dim3(256), 0, st, fb.p, bb.p, nb);
-    launch_gemm(ta != 0, tb != 0, ba.p, bb.p, fc.p, nullptr, nullptr, M, N, K, EPI_NONE, 0, st);
+    launch_gemm(ta != 0, tb != 0, ba.p, ta ? M : K, K, bb.p, tb ? K : N, K, fc.p, nullptr, nullptr, M, N, K,
+                EPI_NONE, 0, st);
     MCHK(hipMemcpy(C, fc.p, nc * sizeof(float), hipMemcpyDeviceToHost));
     return GP_OK;
   } catch (const MlpError& e) {
