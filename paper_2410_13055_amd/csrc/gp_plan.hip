@@ -137,7 +137,7 @@ struct ScenHost {
 struct Tune {
   double bsuff = 0.2;     // restart when the KKT residual fell by this factor
   double bnec = 0.8;      // ... or by this factor and stopped improving
-  double art = 0.2;       // ... or the cycle is this fraction of all iterations
+  double art = 0.05;      // ... or the cycle is this fraction of the iterations since the cold start
   double pw_theta = 0.5;  // smoothing of the primal-weight update
   // primal-weight rule at a restart: 0 balance the weighted primal and dual
   // movement; 1 balance r_bal against max(r_dual, r_gap); 3 balance
