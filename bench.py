@@ -327,6 +327,82 @@ def mlp_leg(args):
     plan.close()
 
 
+def plan_warm_leg(args):
+    """The paper's own warm start (Section 3.2, Fig. 3 analogue): plans under
+    several carbon weights, each from the no-expansion capacities (cold) and
+    from the plan found at 200 $/t (warm).  Projected SGD with batches of 4
+    of 16 scenarios; the full objective is evaluated on all scenarios every
+    `--pw-eval` steps; a run has converged at the first evaluation within 2 %
+    of the best loss of the cold run at the same weight.  Speedup = cold
+    steps / warm steps."""
+    import numpy as np
+    import torch
+
+    from paper_2410_13055_amd import cases, gridplan
+
+    case = cases.geo100()
+    S = len(case.scenarios)
+    pool = list(range(S))
+    lo, hi = case.eta_min(), case.eta_max()
+    gamma = case.gamma()
+    w = np.array([sc.weight for sc in case.scenarios])
+    log = lambda *a: print("[plan-warm]", *a, file=sys.stderr, flush=True)  # noqa: E731
+    # batches change every step: a fixed sweep configuration skips re-tuning
+    plan = gridplan.Plan(case, gridplan.options(block=256, variant=1, check_every=64),
+                         stream=gridplan.current_stream())
+
+    def phi(eta, omega):
+        _, st, rc = plan.solve(eta, pool, warm=1)
+        h = np.array([x["cost"] + omega * x["emis"] for x in st])
+        return float(gamma @ eta + np.mean(w * h))
+
+    plan.solve(lo, pool[:4], warm=0)
+    g0, _, _ = plan.grad(pool[:4], 200.0)
+    alpha = 0.1 * float((hi - lo).min()) / float(np.abs(gamma + g0).max())
+
+    def run(eta0, omega, steps, seed, target=None):
+        rng = np.random.default_rng(seed)
+        eta = eta0.copy()
+        curve = [(0, phi(eta, omega))]
+        t0 = time.perf_counter()
+        for k in range(1, steps + 1):
+            scen = sorted(rng.choice(pool, 4, replace=False).tolist())
+            eta, _, _, rc = plan.step(alpha, scen, gamma, eta, omega=omega, warm=1)
+            if k % args.pw_eval == 0:
+                curve.append((k, phi(eta, omega)))
+                log(f"omega {omega} step {k}: objective {curve[-1][1]:.6e}")
+                if target is not None and curve[-1][1] <= target:
+                    break
+        torch.cuda.synchronize()
+        return eta, curve, time.perf_counter() - t0
+
+    def first_within(curve, best):
+        return next(k for k, v in curve if v <= 1.02 * best)
+
+    log(f"step size {alpha:.4g}; cold run at 200 $/t, the warm source")
+    src, curve200, _ = run(lo, 200.0, args.pw_steps, 200)
+    res = {}
+    for omega in args.pw_omegas:
+        _, cc, tc = run(lo, omega, args.pw_steps, int(omega))
+        best = min(v for _, v in cc)
+        kc = first_within(cc, best)
+        _, wc, tw = run(src, omega, args.pw_steps, int(omega) + 1, target=1.02 * best)
+        kw = next((k for k, v in wc if v <= 1.02 * best), None)
+        res[str(omega)] = {"cold_steps": kc, "warm_steps": kw, "best_cold_loss": best,
+                           "warm_start_loss": wc[0][1], "speedup": (kc / kw) if kw else None,
+                           "cold_s": round(tc, 2), "warm_s": round(tw, 2)}
+        log(f"omega {omega}: cold {kc} steps, warm {kw} steps (warm start at {wc[0][1] / best:.4f} of the best)")
+    sp = [r["speedup"] for r in res.values() if r["speedup"]]
+    out = {"metric": "planning steps to within 2 % of the best cold loss, cold / warm (plan-level warm start)",
+           "value": round(float(np.mean(sp)), 2) if sp else None, "unit": "x",
+           "config": {"workload": "geo100: 100 nodes, 150 lines, 417 generators, 42 batteries, T=24, "
+                                  "16 scenarios; SGD batches of 4; warm from the 200 $/t plan",
+                      "steps": args.pw_steps, "eval_every": args.pw_eval, "alpha": alpha},
+           "by_carbon_weight": res}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
 def warm_start_leg(args):
     """s/gradient step on the 1000-node workload, cold vs learned warm (with
     the previous-iterate warm start as the extra baseline).
@@ -473,6 +549,11 @@ def main():
                          "each kernel and a 1 GiB device copy that calibrates the byte counters")
     ap.add_argument("--no-hbm-case", dest="hbm_case", action="store_false",
                     help="skip timing the sweeps on 16 scenarios of the 1000-node workload")
+    ap.add_argument("--plan-warm", action="store_true",
+                    help="the paper's plan-level warm start on a 100-node case (cold vs warm planning steps)")
+    ap.add_argument("--pw-steps", type=int, default=200)
+    ap.add_argument("--pw-eval", type=int, default=5)
+    ap.add_argument("--pw-omegas", type=float, nargs="+", default=[100.0, 150.0, 250.0, 300.0])
     ap.add_argument("--mlp", action="store_true",
                     help="time the warm-start network's forward pass on 128,000 rows (its MFMA roofline)")
     ap.add_argument("--warm-start", action="store_true",
@@ -513,6 +594,9 @@ def main():
         return
     if args.mlp:
         mlp_leg(args)
+        return
+    if args.plan_warm:
+        plan_warm_leg(args)
         return
     case = cases.by_id(args.config)
     scen = list(range(len(case.scenarios)))

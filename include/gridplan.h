@@ -167,6 +167,10 @@ int dispatch_solve_batch(gp_plan* p, const double* eta, const int32_t* scen, int
  *   (1/nb) sum_s w_s h_s(x*_s(eta)),  h_s = c_s + omega * emissions,
  * with respect to eta, for the scenarios of the last dispatch_solve_batch
  * call (scen must equal that list).  The gamma term is not included.
+ * For omega > 0 the emission part solves an adjoint QP with the same
+ * iteration and stopping triple, the gap measured relative to
+ * 1 + max(|P|, |D|, |D(0)|) (its optimum can sit near zero); returns
+ * GP_ENOTCONVERGED (gradient written) if it misses opt.tol.
  * grad_out: [K] host FP64.  h_out: nullable, receives the weighted mean
  * planner objective.  Errors: GP_ESTATE when no matching solve exists. */
 int dispatch_grad(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,

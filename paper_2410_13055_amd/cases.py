@@ -284,6 +284,13 @@ def config4(seed=None, S=128, storage_price=250.0) -> Case:
                          storage_price=storage_price, seed=seed)
 
 
+def geo100(seed=None, S=16) -> Case:
+    """100-node geometric network (150 lines), 417 generators, 42 batteries,
+    T = 24, 16 scenarios: the size of the paper's warm-start study (Section
+    3.2), with the generator and battery ratios of the other workloads."""
+    return _uniform_case("geo100", 5, 100, 417, 42, 24, S, "geo", seed=seed)
+
+
 def config2(seed=None, S=64) -> Case:
     """64 scenarios of uneven shape: each scenario its own network with
     N ~ U{100..500}, L = 1.5N, G = round(4.17N), B = round(0.417N) and

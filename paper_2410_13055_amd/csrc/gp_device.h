@@ -23,6 +23,8 @@ enum Stat {
   ST_FUEL = 10,     // sum cost_g p
   ST_RES2 = 11,     // sum (E x - e)^2 over all rows
   ST_DUAL2 = 12,    // sum (E'y - q - r x)^2 over free entries
+  ST_D0 = 13,       // dual function at y = 0 (its box terms): the objective's
+                    // scale when the optimum is near zero (adjoint solves)
 };
 constexpr int kMaxStats = 5;  // slots [0, kMaxStats) are maxima, the rest sums
 

@@ -647,6 +647,8 @@ __device__ __forceinline__ void var_stats(double (&v)[kStats], double x, double 
   double xy = (ey - q) / r;
   xy = fmin(fmax(xy, lo), hi);
   v[ST_D] += q * xy + 0.5 * r * xy * xy - ey * xy;
+  const double x0y = fmin(fmax(-q / r, lo), hi);
+  v[ST_D0] += q * x0y + 0.5 * r * x0y * x0y;
   if (lo == -HUGE_VAL && hi == HUGE_VAL) {
     const double dr = ey - q - r * x;
     v[ST_DUAL_MAX] = fmax(v[ST_DUAL_MAX], fabs(dr));

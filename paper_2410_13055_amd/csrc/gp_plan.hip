@@ -870,8 +870,11 @@ Kkt kkt_of(const gp_plan* p, const double* st, double einf, double e2 = 0.0, dou
   k.r_soc = st[ST_RESS_MAX] / den;
   k.r_pri = std::max(k.r_bal, std::max(k.r_flow, k.r_soc));
   k.r_dual = st[ST_DUAL_MAX] / (1.0 + p->qinf);
-  const double P = st[ST_P], D = st[ST_D];
-  k.r_gap = std::fabs(P - D) / (1.0 + std::max(std::fabs(P), std::fabs(D)));
+  // the gap relative to the objective's scale: max(|P|, |D|), or |D(0)| when
+  // that is larger (an adjoint whose solution is near zero has P, D ~ 0
+  // while its dual function at zero measures the size of its data)
+  const double P = st[ST_P], D = st[ST_D], D0 = st[ST_D0];
+  k.r_gap = std::fabs(P - D) / (1.0 + std::max(std::max(std::fabs(P), std::fabs(D)), std::fabs(D0)));
   k.kkt = std::max(k.r_pri, std::max(k.r_dual, k.r_gap));
   const double rp2 = std::sqrt(st[ST_RES2]) / (1.0 + (einf < 0 ? st[ST_XMAX] : e2));
   const double rd2 = std::sqrt(st[ST_DUAL2]) / (1.0 + q2);
