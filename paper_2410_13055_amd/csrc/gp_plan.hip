@@ -200,6 +200,7 @@ struct gp_plan {
   int nvt = 0, nrt = 0;
   DevBuf<Tile> d_svt, d_srt;   // sweep tiles (four hours per thread where T allows)
   int nsvt = 0, nsrt = 0;
+  std::vector<int> sweep_scen;  // scenarios in the sweep tables
   DevBuf<int32_t> d_ranges, d_bscen;
   DevBuf<double> d_part_v, d_part_r, d_stats;
   PinBuf<double> h_stats;
@@ -637,12 +638,53 @@ void drop_graph(gp_plan* p) {
   p->graph_mode = -1;
 }
 
+// Sweep tables (four hours per thread when T allows it) over the listed
+// scenarios only; the iteration narrows them to the unconverged scenarios
+// as the batch converges, so finished scenarios cost no empty blocks.
+void build_sweep_tiles(gp_plan* p, const std::vector<int>& subset) {
+  const int bs = block_size(p);
+  std::vector<Tile> svt, srt;
+  for (int s : subset) {
+    const ScenHost& sh = p->scen[s];
+    const NetHost& n = p->nets[sh.net];
+    const int T = sh.T;
+    const bool v4 = T % 4 == 0;
+    const int w = v4 ? 4 * bs : bs;
+    const int flag = v4 ? kTileVec4 : 0;
+    auto adds = [&](std::vector<Tile>& dst, int cls, int64_t count) {
+      for (int64_t st = 0; st < count; st += w)
+        dst.push_back(Tile{s, cls | flag, (int32_t)st, (int32_t)std::min<int64_t>(w, count - st)});
+    };
+    adds(svt, VC_GEN, (int64_t)n.G * T);
+    adds(svt, VC_LINE, (int64_t)n.L * T);
+    adds(svt, VC_NODE, (int64_t)n.N * T);
+    adds(svt, VC_BATT, (int64_t)n.B * T);
+    adds(srt, RC_BAL, (int64_t)n.N * T);
+    adds(srt, RC_FLOW, (int64_t)n.L * T);
+    for (int k = 0; k < n.B; ++k) srt.push_back(Tile{s, RC_SOC, k, 1});
+  }
+  if ((int64_t)svt.size() > INT32_MAX / 2 || (int64_t)srt.size() > INT32_MAX / 2) fail(GP_EINVAL, "batch too large");
+  hipStream_t st = p->stream;
+  p->d_svt.upload(svt, st);
+  p->d_srt.upload(srt, st);
+  p->nsvt = (int)svt.size();
+  p->nsrt = (int)srt.size();
+  p->sweep_scen = subset;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
 // tiles of the batch: per scenario, variable tiles [gens | lines | nodes |
 // batteries] and row tiles [balance | flow | one per battery chain]
 void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) {
-  if (!force && batch == p->batch && p->nvt > 0) return;
+  if (!force && batch == p->batch && p->nvt > 0) {
+    if (p->sweep_scen != batch) {  // narrowed by an interrupted iteration
+      build_sweep_tiles(p, batch);
+      drop_graph(p);
+    }
+    return;
+  }
   const int bs = block_size(p);
-  std::vector<Tile> vt, rt, svt, srt;
+  std::vector<Tile> vt, rt;
   std::vector<int32_t> ranges;
   for (int s : batch) {
     const ScenHost& sh = p->scen[s];
@@ -660,21 +702,6 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
     add(rt, RC_BAL, (int64_t)n.N * T);
     add(rt, RC_FLOW, (int64_t)n.L * T);
     for (int k = 0; k < n.B; ++k) rt.push_back(Tile{s, RC_SOC, k, 1});
-    // sweep tables: four hours per thread when T allows it
-    const bool v4 = T % 4 == 0;
-    const int w = v4 ? 4 * bs : bs;
-    const int flag = v4 ? kTileVec4 : 0;
-    auto adds = [&](std::vector<Tile>& dst, int cls, int64_t count) {
-      for (int64_t st = 0; st < count; st += w)
-        dst.push_back(Tile{s, cls | flag, (int32_t)st, (int32_t)std::min<int64_t>(w, count - st)});
-    };
-    adds(svt, VC_GEN, (int64_t)n.G * T);
-    adds(svt, VC_LINE, (int64_t)n.L * T);
-    adds(svt, VC_NODE, (int64_t)n.N * T);
-    adds(svt, VC_BATT, (int64_t)n.B * T);
-    adds(srt, RC_BAL, (int64_t)n.N * T);
-    adds(srt, RC_FLOW, (int64_t)n.L * T);
-    for (int k = 0; k < n.B; ++k) srt.push_back(Tile{s, RC_SOC, k, 1});
     ranges.push_back(v0);
     ranges.push_back((int)vt.size());
     ranges.push_back(r0);
@@ -687,10 +714,6 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
   p->d_rt.upload(rt, st);
   p->nvt = (int)vt.size();
   p->nrt = (int)rt.size();
-  p->d_svt.upload(svt, st);
-  p->d_srt.upload(srt, st);
-  p->nsvt = (int)svt.size();
-  p->nsrt = (int)srt.size();
   p->d_ranges.upload(ranges, st);
   std::vector<int32_t> bs_(batch.begin(), batch.end());
   p->d_bscen.upload(bs_, st);
@@ -701,6 +724,7 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
   p->batch = batch;
   drop_graph(p);
   HIPCHK(hipStreamSynchronize(st));
+  build_sweep_tiles(p, batch);
 }
 
 // Asynchronous copies from pinned memory: the caller must synchronise the
@@ -1091,12 +1115,29 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
         if (go_cold[b]) k_restart[b] = rmet_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
       std::fill(go_cold.begin(), go_cold.end(), 0);
     }
+    // narrow the sweeps to the unconverged scenarios once they are at most
+    // half of those swept (the graph is captured again for the new tables)
+    if (remaining > 0 && 2 * remaining <= (int)p->sweep_scen.size() && p->sweep_scen.size() > 1) {
+      std::vector<int> act;
+      for (int b = 0; b < nb; ++b)
+        if (!done[b]) act.push_back(batch[b]);
+      build_sweep_tiles(p, act);
+      drop_graph(p);
+      a.svt = p->d_svt.p;
+      a.srt = p->d_srt.p;
+      a.nsvt = p->nsvt;
+      a.nsrt = p->nsrt;
+    }
     if (p->opt.verbose && (it / ce) % 16 == 0) {
       double worst = 0;
       for (int b = 0; b < nb; ++b)
         if (!done[b]) worst = std::max(worst, out[b].kkt);
       fprintf(stderr, "[gridplan] mode %d iter %d remaining %d worst kkt %.3e\n", mode, it, remaining, worst);
     }
+  }
+  if (p->sweep_scen != batch) {
+    build_sweep_tiles(p, batch);
+    drop_graph(p);
   }
   for (int b = 0; b < nb; ++b) {
     out[b].restarts = nrest[b];

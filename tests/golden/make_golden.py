@@ -9,6 +9,7 @@ gradient of h_s (not weighted) as JSON:
     python tests/golden/make_golden.py 1 0 1      # config 1, scenarios 0 and 1
     python tests/golden/make_golden.py 3 0        # config 3, scenario 0
     python tests/golden/make_golden.py --spread 1 0   # add the kink spread to a stored file
+    python tests/golden/make_golden.py --spread-draw 3 1 0   # one draw of it (draws run in parallel)
 
 The spread is the largest relative change of the oracle gradient when every
 capacity moves by U[-0.02, 0.02] MW (two draws): the GPU solves to a balance
@@ -67,7 +68,41 @@ def spread(cfg, s):
     print(f"config {cfg} scenario {s}: gradient spread {worst:.2e}", flush=True)
 
 
+def spread_draw(cfg, s, k):
+    """One draw k of the spread, merged into the stored file under a lock
+    (several draws can run as separate processes)."""
+    import fcntl
+    case = cases.by_id(cfg)
+    eta = golden_eta(case)
+    off = case.eta_offsets()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_config{cfg}_s{s}.json")
+    net = case.scenarios[s].network
+    rng = np.random.Generator(np.random.PCG64(1000 + k))
+    ep = np.clip(eta + rng.uniform(-SPREAD_MW, SPREAD_MW, size=eta.shape), case.eta_min(), case.eta_max())
+    qp = D.assemble(case, s, ep[off[net]:off[net + 1]])
+    g = Gm.scenario_gradient(qp, D.solve(qp), case.omega)["grad"]
+    with open(path + ".lock", "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        with open(path) as fh:
+            out = json.load(fh)
+        g0 = np.array(out["grad"])
+        draws = dict(out.get("spread_draws", {}))
+        draws[str(k)] = [float(v) for v in g]
+        out["spread_draws"] = draws
+        out["spread_grads"] = [draws[d] for d in sorted(draws)]
+        out["grad_spread"] = max(float(np.linalg.norm(np.array(v) - g0) / np.linalg.norm(g0))
+                                 for v in out["spread_grads"])
+        out["spread_mw"] = SPREAD_MW
+        with open(path, "w") as fh:
+            json.dump(out, fh)
+    os.remove(path + ".lock")
+    print(f"config {cfg} scenario {s} draw {k}: gradient spread so far {out['grad_spread']:.2e}", flush=True)
+
+
 def main():
+    if sys.argv[1] == "--spread-draw":
+        spread_draw(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]))
+        return
     if sys.argv[1] == "--spread":
         for s in sys.argv[3:] or ["0"]:
             spread(int(sys.argv[2]), int(s))
