@@ -587,6 +587,10 @@ __global__ __launch_bounds__(BS) void k_check_rows(Args a) {
   const int tix = blockIdx.x;
   const Tile tl = a.rtiles[tix];
   const int s = tl.scen;
+  if (!a.active[s]) {  // a finished scenario's partials are zero (uniform per block)
+    if ((int)threadIdx.x < kStats) a.part_r[(int64_t)tix * kStats + threadIdx.x] = 0.0;
+    return;
+  }
   double v[kStats];
 #pragma unroll
   for (int q = 0; q < kStats; ++q) v[q] = 0.0;
@@ -663,6 +667,10 @@ __global__ __launch_bounds__(BS) void k_check_vars(Args a) {
   const int tix = blockIdx.x;
   const Tile tl = a.vtiles[tix];
   const int s = tl.scen;
+  if (!a.active[s]) {  // a finished scenario's partials are zero (uniform per block)
+    if ((int)threadIdx.x < kStats) a.part_v[(int64_t)tix * kStats + threadIdx.x] = 0.0;
+    return;
+  }
   double v[kStats];
 #pragma unroll
   for (int q = 0; q < kStats; ++q) v[q] = 0.0;
