@@ -148,7 +148,10 @@ struct Tune {
   // rule 4 counts the gap only up to the balance residual.
   int rule = 4;
   double gain = 0.25;     // exponent of the residual-balancing update
-  int arule = 0;          // rule of the adjoint solve (-1: same as rule)
+  // rule of the adjoint solve (-1: the dispatch rule).  Rule 0 let the
+  // weights swing until adjoint solves on the 100-node case diverged (KKT
+  // growing to 1e6 within the iteration limit); the dispatch rule converges
+  int arule = -1;
   int flow_rule = 1;      // 1: adapt the flow-class multiplier at restarts
   int rmetric = 1;        // restart decisions on 0: the max-norm KKT, 1: the 2-norm KKT
   int stop_norm = 0;      // stopping test on 0: the max-norm KKT, 2: the 2-norm KKT
