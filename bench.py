@@ -266,6 +266,43 @@ def write_warmstart_profile(d):
         fh.write("\n".join(out) + "\n")
 
 
+def write_planwarm_profile(d):
+    """profiles/plan_warm_geo100.md from the JSON lines of `bench.py
+    --plan-warm` runs saved as <d>/pw_*.json (one or more carbon weights
+    each, the same warm source)."""
+    import glob
+    rows, cfg, fails = {}, None, {"solve": 0, "step": 0}
+    for f in sorted(glob.glob(os.path.join(d, "pw_*.json"))):
+        with open(f) as fh:
+            r = json.loads(next(l for l in fh if l.startswith('{"metric"')))
+        cfg = r["config"]
+        rows.update(r["by_carbon_weight"])
+        for k in fails:
+            fails[k] += r.get("unconverged", {}).get(k, 0)
+    out = ["# Plan-level warm start (the paper's Section 3.2 study, synthetic stand-in)", "",
+           "Commands:", "",
+           "    python bench.py --plan-warm --pw-steps 300 --pw-src-steps 150 --pw-omegas 150 --pw-src <src.npy>",
+           "    python bench.py --plan-warm --pw-steps 300 --pw-omegas 100 250 --pw-src <src.npy>", "",
+           f"Workload: {cfg['workload']}; {cfg['steps']} projected-SGD steps per cold run, step "
+           f"{cfg['alpha0']:.4g}/sqrt(k), the full objective evaluated every {cfg['eval_every']} steps.  The warm "
+           "source is the plan after 150 steps at 200 $/t.  A run has converged at its first evaluation within "
+           "2 % of the best loss of the cold run at the same carbon weight.", "",
+           "| carbon weight $/t | cold steps | warm steps | speedup (cold / warm) | warm start / best cold loss | "
+           "cold s | warm s |", "|---|---|---|---|---|---|---|"]
+    sp = []
+    for om in sorted(rows, key=float):
+        r = rows[om]
+        out.append(f"| {float(om):.0f} | {r['cold_steps']} | {r['warm_steps']} | "
+                   f"{r['speedup']:.1f} | {r['warm_start_loss'] / r['best_cold_loss']:.4f} | {r['cold_s']} | "
+                   f"{r['warm_s']} |")
+        if r["speedup"]:
+            sp.append(r["speedup"])
+    out += ["", f"Mean speedup {sum(sp) / len(sp):.1f}x over {len(sp)} carbon weights.  Solves that missed the "
+            f"tolerance in these runs: {fails['step']} step(s), {fails['solve']} evaluation(s)."]
+    with open(os.path.join(ROOT, "profiles", "plan_warm_geo100.md"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
 def hbm_case_sweeps(iters):
     """The sweep kernels on a working set far above the 256 MB Infinity
     Cache: 16 scenarios of the 1000-node workload (a GPU's share of its 128),
@@ -394,7 +431,7 @@ def plan_warm_leg(args):
         log(f"step size {alpha:.4g}; warm source read from {args.pw_src}")
     else:
         log(f"step size {alpha:.4g}; cold run at 200 $/t, the warm source")
-        src, curve200, _ = run(lo, 200.0, args.pw_steps, 200)
+        src, curve200, _ = run(lo, 200.0, args.pw_src_steps or args.pw_steps, 200)
         if args.pw_src:
             np.save(args.pw_src, src)
     res = {}
@@ -572,6 +609,7 @@ def main():
     ap.add_argument("--pw-eval", type=int, default=5)
     ap.add_argument("--pw-omegas", type=float, nargs="+", default=[100.0, 150.0, 250.0, 300.0])
     ap.add_argument("--pw-src", help="file of the 200 $/t plan: read when present, else written")
+    ap.add_argument("--pw-src-steps", type=int, default=0, help="steps of the 200 $/t run (default --pw-steps)")
     ap.add_argument("--mlp", action="store_true",
                     help="time the warm-start network's forward pass on 128,000 rows (its MFMA roofline)")
     ap.add_argument("--warm-start", action="store_true",
@@ -593,6 +631,9 @@ def main():
             write_mlp_profile(args.summarize)
         if os.path.exists(os.path.join(args.summarize, "ws_bench.json")):
             write_warmstart_profile(args.summarize)
+        import glob
+        if glob.glob(os.path.join(args.summarize, "pw_*.json")):
+            write_planwarm_profile(args.summarize)
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
