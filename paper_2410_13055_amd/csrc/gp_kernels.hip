@@ -151,16 +151,28 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
     const float* pf = xs + (int64_t)nt.G * TT;
     const float* pch = xs + (int64_t)(nt.G + nt.L + nt.N) * TT;
     const float* pdis = pch + (int64_t)nt.B * TT;
-    for (int e = e0; e < e1; ++e) {
-      const int code = a.term[e];
+    // signed injection of one terminal (generator, battery, line end)
+    auto inj = [&](int code) -> f4 {
       const int64_t o = (int64_t)(code >> 2) * TT + t;
       switch (code & 3) {
-        case TT_GEN: res += ld4(xs + o); break;
-        case TT_BATT: res += ld4(pdis + o) - ld4(pch + o); break;
-        case TT_LINE_TO: res += ld4(pf + o); break;
-        default: res -= ld4(pf + o); break;
+        case TT_GEN: return ld4(xs + o);
+        case TT_BATT: return ld4(pdis + o) - ld4(pch + o);
+        case TT_LINE_TO: return ld4(pf + o);
+        default: return -ld4(pf + o);
       }
+    };
+    int e = e0;
+    // four terminals at a time: their loads are issued before the sums,
+    // which keep the terminal order
+    for (; e + 4 <= e1; e += 4) {
+      const int c0 = a.term[e], c1 = a.term[e + 1], c2 = a.term[e + 2], c3 = a.term[e + 3];
+      const f4 v0 = inj(c0), v1 = inj(c1), v2 = inj(c2), v3 = inj(c3);
+      res += v0;
+      res += v1;
+      res += v2;
+      res += v3;
     }
+    for (; e < e1; ++e) res += inj(a.term[e]);
     const double f = c * (double)a.sig_bal[nt.node_off + n];
 #pragma unroll
     for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
