@@ -8,7 +8,7 @@
 //
 // GEMM: C[M x N] = op(A)[M x K] op(B)[K x N] with op = transpose or not,
 // row-major storage, zero-filled edges (no padding required).  Block tile
-// 128 x 128 x 32, 256 threads = 4 wavefronts of 64 x 64 (2 x 2 tiles of the
+// 128 x 128 x 64, 256 threads = 4 wavefronts of 64 x 64 (2 x 2 tiles of the
 // 32 x 32 x 16 BF16 MFMA).  Operand layout of v_mfma_f32_32x32x16_bf16: lane l
 // holds row (l mod 32) of A and column (l mod 32) of B for k in
 // [8 (l div 32), 8 (l div 32) + 8); accumulator register v of lane l is
@@ -50,6 +50,7 @@ struct GemmArgs {
   int Ka, Kb;        // entries of A / B with k >= Ka / Kb read as zero
   int epi, accumulate;
   int vecA, vecB;    // 1: stage 8 contiguous elements per 16-byte load
+  int vecC;          // 1: BF16 output written as 16-byte segments through LDS
 };
 
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -121,14 +122,31 @@ __device__ __forceinline__ void store_chunks(__bf16* __restrict__ S, const Chunk
 // 32x32x16 MFMA.  Block tile BM x 128 x 64 with 4 wavefronts in 2 x 2, each
 // owning (BM/2) x 64 of C; the next K tile is fetched into registers while
 // the current one is multiplied.
+//
+// Tile order: the grid is 1-D and workgroups go to the 8 XCDs round-robin
+// (workgroup b to XCD b mod 8), so XCD x is given the contiguous range of
+// tiles [x q + min(x, r), ...) (q = tiles / 8, r = tiles mod 8) in row-panel
+// order: the column tiles of one row panel of A run on one XCD at about the
+// same time and share its L2, and A is fetched from HBM about once.
+//
+// BF16 output (hidden layers) is staged through LDS after the last K tile and
+// written as 16-byte row segments; FP32 output is written from the
+// accumulators directly.
 template <int BM, bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   static_assert(BM == 64 || BM == 128, "BM");
   constexpr int MI = BM / 64;  // 32-row MFMA tiles per wave along m
-  __shared__ __attribute__((aligned(16))) __bf16 As[BM * LDA];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN * LDA];
+  constexpr int CP = BN + 8;   // row pitch of the staged C tile (bf16)
+  static_assert(BM * CP <= (BM + BN) * LDA, "the C tile fits in the operand tiles");
+  __shared__ __attribute__((aligned(16))) __bf16 smem[(BM + BN) * LDA];
+  __bf16* As = smem;
+  __bf16* Bs = smem + BM * LDA;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int gn = (g.N + BN - 1) / BN;
+  const int tiles = gn * ((g.M + BM - 1) / BM);
+  const int xcd = (int)blockIdx.x & 7, q = tiles >> 3, r8 = tiles & 7;
+  const int tile = xcd * q + min(xcd, r8) + ((int)blockIdx.x >> 3);
+  const int m0 = (tile / gn) * BM, n0 = (tile % gn) * BN;
   const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * 64;
   f32x16 acc[MI][2];
 #pragma unroll
@@ -167,7 +185,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
     __syncthreads();
   }
-  // epilogue
+  if (g.Cb && !g.Cf && g.vecC) {
+    // the loop ended on a barrier, so the operand tiles are free for C
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int cl = wn + 32 * j + (lane & 31);
+        const float bv = (g.epi != EPI_NONE && n0 + cl < g.N) ? g.bias[n0 + cl] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int rl = wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          float r = acc[i][j][v] + bv;
+          if (g.epi == EPI_BIAS_RELU) r = fmaxf(r, 0.f);
+          smem[rl * CP + cl] = to_bf16(r);
+        }
+      }
+    __syncthreads();
+    // N is a multiple of 8, so a segment starting inside the matrix ends inside it
+#pragma unroll
+    for (int c = 0; c < BM * BN / 8 / 256; ++c) {
+      const int e = (int)threadIdx.x + 256 * c;
+      const int rl = e / (BN / 8), cl = (e % (BN / 8)) * 8;
+      if (m0 + rl < g.M && n0 + cl < g.N)
+        *reinterpret_cast<u16x8*>(g.Cb + (int64_t)(m0 + rl) * g.N + n0 + cl) =
+            *reinterpret_cast<const u16x8*>(&smem[rl * CP + cl]);
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -376,16 +421,18 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // finite only if Kb bounds them).
 void launch_gemm(bool ta, bool tb, const __bf16* A, int lda, int Ka, const __bf16* B, int ldb, int Kb, float* Cf,
                  __bf16* Cb, const float* bias, int M, int N, int K, int epi, int accumulate, hipStream_t st) {
-  GemmArgs g{A, B, Cf, Cb, bias, M, N, K, lda, ldb, Ka, Kb, epi, accumulate, 0, 0};
+  GemmArgs g{A, B, Cf, Cb, bias, M, N, K, lda, ldb, Ka, Kb, epi, accumulate, 0, 0, 0};
   // 16-byte staging needs every chunk to start on a multiple of 8 elements
   // of an aligned base and to lie wholly inside or outside the valid range
   g.vecA = aligned16(A) && lda % 8 == 0 && (ta ? M % 8 == 0 : Ka % 8 == 0);
   g.vecB = aligned16(B) && ldb % 8 == 0 && (tb ? Kb % 8 == 0 : N % 8 == 0);
+  g.vecC = Cb && aligned16(Cb) && N % 8 == 0;
   const int gn = (N + BN - 1) / BN;
   const bool small = (int64_t)gn * ((M + 127) / 128) < 512;  // fill the CUs with 64-row tiles
+  if ((int64_t)gn * ((M + 63) / 64) > INT32_MAX) mfail(GP_EINVAL, "GEMM of %d x %d has too many tiles", M, N);
 #define GEMM_(BMv)                                                                                 \
   {                                                                                                \
-    dim3 grid(gn, (M + BMv - 1) / BMv);                                                            \
+    dim3 grid(gn * ((M + BMv - 1) / BMv));                                                         \
     if (!ta && !tb) hipLaunchKernelGGL((k_gemm<BMv, false, false>), grid, dim3(256), 0, st, g);     \
     else if (!ta && tb) hipLaunchKernelGGL((k_gemm<BMv, false, true>), grid, dim3(256), 0, st, g);  \
     else if (ta && !tb) hipLaunchKernelGGL((k_gemm<BMv, true, false>), grid, dim3(256), 0, st, g);  \
