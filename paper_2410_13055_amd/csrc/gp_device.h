@@ -47,7 +47,7 @@ struct Tile {
   int32_t scen;   // scenario index
   int32_t cls;    // VarClass or RowClass (sweep tables: | kTileVec4)
   int32_t start;  // first local item (VC_* / RC_BAL / RC_FLOW) or battery index (RC_SOC)
-  int32_t count;  // items in this tile (RC_SOC: chains, each its own block)
+  int32_t count;  // items in this tile (RC_SOC: chains; one per block unless four hours per thread)
 };
 
 struct ScenDev {

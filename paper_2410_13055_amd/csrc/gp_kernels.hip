@@ -190,6 +190,82 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
   }
 }
 
+// Battery chains, four hours per thread: T/4 threads per chain and as many
+// chains per block as fit (tile start = first battery, count = chains).  The
+// chain's duals are loaded before the barrier, so their latency overlaps that
+// of the residual loads.  Each chain's residuals sit in LDS with their
+// cyclic continuation (2T floats per chain: r at [o, o + T) and the wrapped
+// copies around it, o = J for the symmetric taps, 0 for the full row), so the
+// four rows of a thread accumulate side by side without index wrapping; each
+// row's sum keeps the term order of the one-chain-per-block form.
+// sres: LDS of 2 T count floats.  Every thread of the block must call it.
+__device__ __forceinline__ void soc_chains4(const Args& a, const Tile& tl, const ScenDev& sc, const NetDev& nt,
+                                            double c, double lam, int check, float* sres) {
+  const int T = sc.T, T4 = T >> 2;
+  const int64_t TT = T;
+  const int J = sc.ntap - 1;
+  const bool full = 2 * J + 1 >= T;  // taps cover the whole chain
+  const int o = full ? 0 : J;
+  const int ch = (int)threadIdx.x / T4, t0 = 4 * ((int)threadIdx.x - ch * T4);
+  const bool on = ch < tl.count;
+  float* e = sres + 2 * ch * T;
+  double yv[4], y0[4];
+  int64_t row = 0;
+  if (on) {
+    const int kb = tl.start + ch;
+    row = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)kb * TT + t0;
+    ldd4(a.y + row, yv);
+    ldd4(a.y0 + row, y0);
+    const float* pch = a.x + sc.xoff + (int64_t)(nt.G + nt.L + nt.N) * TT + (int64_t)kb * TT;
+    const float* pdis = pch + (int64_t)nt.B * TT;
+    const float* psoc = pdis + (int64_t)nt.B * TT;
+    const f4 so = ld4(psoc + t0), cv = ld4(pch + t0), dv = ld4(pdis + t0);
+    const float sp = psoc[t0 == 0 ? T - 1 : t0 - 1];
+    const f4 prev = {sp, so[0], so[1], so[2]};
+    const f4 r = so - prev - a.eff * cv + dv;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u;
+      e[o + t] = r[u];
+      if (full || t < J) e[o + T + t] = r[u];  // continuation past the end
+      if (!full && t >= T - J) e[t - (T - J)] = r[u];  // and before the start
+    }
+  }
+  __syncthreads();
+  if (!on) return;
+  const float* h = a.taps + sc.tap_off;
+  float acc[4];
+  if (full) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = 0.f;
+    for (int jj = 0; jj < T; ++jj) {
+      const float hv = h[jj];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += hv * e[t0 + u + jj];
+    }
+  } else {
+    const float* m = e + o + t0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = h[0] * m[u];
+#pragma unroll 4
+    for (int jj = 1; jj <= J; ++jj) {
+      const float hv = h[jj];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += hv * (m[u + jj] + m[u - jj]);
+    }
+  }
+  double yh[4], e2[4], yn[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    yh[u] = yv[u] - c * (double)acc[u];
+    e2[u] = 2.0 * yh[u] - yv[u];
+    yn[u] = lam * e2[u] + (1.0 - lam) * y0[u];
+  }
+  std4(a.ybar + row, e2);
+  std4(a.y + row, yn);
+  if (check) std4(a.yhat + row, yh);
+}
+
 // One row tile of the dual sweep.  sres: LDS of at least T floats.  Every
 // thread of the block must call it (the SOC-chain branch synchronises).
 template <int BS>
@@ -205,6 +281,10 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
   const int k = a.kbase[s] + j;
   const double lam = (double)(k + 1) / (double)(k + 2);
   const float* xs = a.x + sc.xoff;
+  if (tl.cls == (RC_SOC | kTileVec4)) {
+    soc_chains4(a, tl, sc, nt, c, lam, check, sres);
+    return;
+  }
   if (tl.cls & kTileVec4) {
     dual_rows4(a, tl, sc, nt, c, lam, check);
     return;
@@ -1058,7 +1138,9 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
 // `qblocks` resident blocks (q: two counter pairs, dual then primal)
 hipError_t launch_dual(const Args& a, int bs, int j, int check, int max_T, hipStream_t st, int timed,
                        int variant, int qblocks, unsigned long long* qc, unsigned int* qd) {
-  const size_t sh = (size_t)max_T * sizeof(float);
+  // one chain of up to max_T hours, or chains of four hours per thread at
+  // 2T floats each (at most 8 bs floats)
+  const size_t sh = (size_t)std::max(max_T, 8 * bs) * sizeof(float);
   if (variant == 1) {
     const int g = std::min(qblocks, a.nsrt);
 #define L_(B)                                                                                   \

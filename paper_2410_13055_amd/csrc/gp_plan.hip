@@ -664,7 +664,12 @@ void build_sweep_tiles(gp_plan* p, const std::vector<int>& subset) {
     adds(svt, VC_BATT, (int64_t)n.B * T);
     adds(srt, RC_BAL, (int64_t)n.N * T);
     adds(srt, RC_FLOW, (int64_t)n.L * T);
-    for (int k = 0; k < n.B; ++k) srt.push_back(Tile{s, RC_SOC, k, 1});
+    // battery chains: T/4 threads per chain, as many chains per block as fit
+    const int cpb = v4 ? bs / (T / 4) : 0;
+    if (cpb > 0)
+      for (int k = 0; k < n.B; k += cpb) srt.push_back(Tile{s, RC_SOC | kTileVec4, k, std::min(cpb, n.B - k)});
+    else
+      for (int k = 0; k < n.B; ++k) srt.push_back(Tile{s, RC_SOC, k, 1});
   }
   if ((int64_t)svt.size() > INT32_MAX / 2 || (int64_t)srt.size() > INT32_MAX / 2) fail(GP_EINVAL, "batch too large");
   hipStream_t st = p->stream;
