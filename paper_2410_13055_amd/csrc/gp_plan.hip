@@ -1125,9 +1125,10 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
         if (go_cold[b]) k_restart[b] = rmet_of(kkt_of(p, p->h_stats.p + (size_t)b * kStats, einf[b], e2[b], q2[b]));
       std::fill(go_cold.begin(), go_cold.end(), 0);
     }
-    // narrow the sweeps to the unconverged scenarios once they are at most
-    // half of those swept (the graph is captured again for the new tables)
-    if (remaining > 0 && 2 * remaining <= (int)p->sweep_scen.size() && p->sweep_scen.size() > 1) {
+    // narrow the sweeps to the unconverged scenarios whenever one of those
+    // swept has converged (the graph is captured again for the new tables;
+    // at most one rebuild per scenario and solve)
+    if (remaining > 0 && remaining < (int)p->sweep_scen.size()) {
       std::vector<int> act;
       for (int b = 0; b < nb; ++b)
         if (!done[b]) act.push_back(batch[b]);
