@@ -33,7 +33,11 @@ def test_gemm_matches_bf16_reference(ta, tb, M_, N_, K_):
     assert np.all(np.abs(C - ref) <= 2e-5 * scale + 1e-30)
 
 
-@pytest.mark.parametrize("dims,rows", [([53, 64, 64, 24], 300), ([843, 512, 512, 512, 336], 512)])
+# widths that are multiples of 8 take the LDS-staged BF16 epilogue, width 60
+# the element-wise one; 17,000 rows of width 512 fill the GPU with 128-row
+# tiles and end on a ragged tile (17,000 = 132 x 128 + 104)
+@pytest.mark.parametrize("dims,rows", [([53, 64, 64, 24], 300), ([843, 512, 512, 512, 336], 512),
+                                       ([53, 60, 60, 24], 300), ([200, 512, 512, 24], 17000)])
 def test_network_forward_loss_and_gradient_match_reference(dims, rows):
     gb = _gb()
     net = gb.MLP(dims[0], dims[1], len(dims) - 2, dims[-1], seed=1)
