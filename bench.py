@@ -239,6 +239,47 @@ def write_mlp_profile(d):
         fh.write("\n".join(out) + "\n")
 
 
+def write_timeline_profile(d):
+    """profiles/solve_timeline_geo240.md from <d>/trace_gap (a kernel trace,
+    without --stats, of one cold solve of the headline workload): how much
+    of the solve the GPU is busy, and where the idle time sits."""
+    import collections
+    import csv
+    import gzip
+    path = os.path.join(d, "trace_gap", "run_kernel_trace.csv")
+    fh = gzip.open(path + ".gz", "rt") if os.path.exists(path + ".gz") else open(path)
+    with fh:
+        ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"].split("(")[0])
+                    for r in csv.DictReader(fh))
+    sweeps = [e for e in ev if e[2].startswith(("void gp::k_primal<", "void gp::k_dual<")) and e[2].endswith(", 0>")]
+    t0, t1 = sweeps[0][0], sweeps[-1][1]
+    inside = [e for e in ev if e[0] >= t0 and e[1] <= t1]
+    busy = sum(e[1] - e[0] for e in inside)
+    gaps = [inside[i + 1][0] - inside[i][1] for i in range(len(inside) - 1)]
+    big = [g for g in gaps if g > 20000]
+    per = collections.defaultdict(lambda: [0, 0])
+    for e in inside:
+        per[e[2]][0] += 1
+        per[e[2]][1] += e[1] - e[0]
+    span = t1 - t0
+    out = ["# Timeline of one cold solve: geo240, 240 nodes, 16 scenarios, T=168 (first solve of the run, "
+           "autotuning included)", "",
+           "Command (from /tmp, TMPDIR=/tmp):", "",
+           "    rocprofv3 --kernel-trace --output-format csv -d <out>/trace_gap -o run -- "
+           "python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu --no-hbm-case",
+           "    python bench.py --summarize <out>", "",
+           f"From the first to the last sweep launch: {span / 1e6:.1f} ms, {len(inside)} kernels, GPU busy "
+           f"{busy / 1e6:.1f} ms ({100.0 * busy / span:.1f} %).  Gaps above 20 us between kernels: {len(big)}, "
+           f"{sum(big) / 1e6:.1f} ms in all (the host reading each chunk's check statistics and deciding "
+           f"restarts, narrowing and graph re-captures); the rest of the idle time is spread over launch gaps "
+           f"inside the replayed graphs.", "",
+           "| kernel | launches | total ms | share of span |", "|---|---|---|---|"]
+    for k, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1])[:10]:
+        out.append(f"| `{k[:70]}` | {c} | {t / 1e6:.1f} | {100.0 * t / span:.1f} % |")
+    with open(os.path.join(ROOT, "profiles", "solve_timeline_geo240.md"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
 def write_warmstart_profile(d):
     """profiles/warmstart_geo1000.md from <d>/ws_bench.json (the JSON line of
     `bench.py --warm-start`) and its per-step log."""
@@ -631,6 +672,8 @@ def main():
             write_mlp_profile(args.summarize)
         if os.path.exists(os.path.join(args.summarize, "ws_bench.json")):
             write_warmstart_profile(args.summarize)
+        if os.path.exists(os.path.join(args.summarize, "trace_gap")):
+            write_timeline_profile(args.summarize)
         import glob
         if glob.glob(os.path.join(args.summarize, "pw_*.json")):
             write_planwarm_profile(args.summarize)
