@@ -1229,61 +1229,53 @@ __device__ __forceinline__ void node_avail(const Args& a, const NetDev& nt, cons
   const int e0 = a.term_ptr[nt.tptr_off + n], e1 = a.term_ptr[nt.tptr_off + n + 1];
   ren = 0.f;
   thr = 0.f;
-  for (int e = e0; e < e1; ++e) {
-    const int code = a.term[e];
-    if ((code & 3) != TT_GEN) continue;
-    const int g = code >> 2;
-    const float cap = a.avail[sc.aoff + (int64_t)g * sc.T + t] * a.eta[nt.eta_off + g];
-    if (a.gen_cost[nt.gen_off + g] > 0.f) thr += cap;
-    else ren += cap;
+  // four terminals at a time: their loads are issued before the sums, which
+  // keep the terminal order
+  for (int e = e0; e < e1; e += 4) {
+    const int cnt = min(4, e1 - e);
+    int code[4];
+    float cap[4], cost[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) code[m] = m < cnt ? a.term[e + m] : 1;  // 1: not a generator
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if ((code[m] & 3) == TT_GEN) {
+        const int g = code[m] >> 2;
+        cap[m] = a.avail[sc.aoff + (int64_t)g * sc.T + t] * a.eta[nt.eta_off + g];
+        cost[m] = a.gen_cost[nt.gen_off + g];
+      }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if ((code[m] & 3) == TT_GEN) {
+        if (cost[m] > 0.f) thr += cap[m];
+        else ren += cap[m];
+      }
   }
 }
 
-__global__ void k_features(Args a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, float* X) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // thread per (row, t): rows are flattened over the batch
-  const int64_t row = gid / T;
-  const int t = (int)(gid - row * T);
-  // find the batch entry of this row
-  int b = -1;
-  for (int q = 0; q < nb; ++q) {
-    const int s = bscen[q];
-    const int r0 = rowoff[s];
-    const int N = a.net[a.scen[s].net].N;
-    if (row >= r0 && row < r0 + N) {
-      b = q;
-      break;
-    }
-  }
-  if (b < 0) return;
-  const int s = bscen[b];
+// Features in two passes, one thread per (row, t).  The first writes the
+// node's own columns (load, renewable and thermal available capacity, and
+// at t = 0 the three capacities); the second sums the neighbours' load and
+// the (scaled) renewable capacity the first pass wrote in their rows, so no
+// terminal list is walked more than once per (row, t).
+__global__ void k_features_own(Args a, const int32_t* bscen, const int32_t* rowoff, int T, float* X) {
+  const int s = bscen[blockIdx.y];
   const ScenDev sc = a.scen[s];
   const NetDev nt = a.net[sc.net];
-  const int n = (int)(row - rowoff[s]);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = (int)(gid / T), t = (int)(gid - (int64_t)n * T);
+  if (n >= nt.N) return;
+  const int64_t row = rowoff[s] + n;
   const int F = 5 * T + 3;
   float* x = X + row * F;
   const float sc100 = 0.01f;
   float ren, thr;
   node_avail(a, nt, sc, n, t, ren, thr);
-  float nl = 0.f, nren = 0.f, lcap = 0.f;
-  const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int code = a.ang[e];
-    const int l = code >> 1;
-    const int m = (code & 1) ? a.line_to[nt.line_off + l] : a.line_from[nt.line_off + l];
-    nl += a.load[sc.doff + (int64_t)m * T + t];
-    float r2, t2;
-    node_avail(a, nt, sc, m, t, r2, t2);
-    nren += r2;
-    lcap += a.eta[nt.eta_off + nt.G + l];
-  }
   x[t] = a.load[sc.doff + (int64_t)n * T + t] * sc100;
   x[T + t] = ren * sc100;
   x[2 * T + t] = thr * sc100;
-  x[3 * T + t] = nl * sc100;
-  x[4 * T + t] = nren * sc100;
   if (t == 0) {
-    float bcap = 0.f, gcap = 0.f;
+    float bcap = 0.f, gcap = 0.f, lcap = 0.f;
     const int f0 = a.term_ptr[nt.tptr_off + n], f1 = a.term_ptr[nt.tptr_off + n + 1];
     for (int e = f0; e < f1; ++e) {
       const int code = a.term[e];
@@ -1291,30 +1283,46 @@ __global__ void k_features(Args a, const int32_t* bscen, int nb, const int32_t* 
       if ((code & 3) == TT_GEN && a.gen_cost[nt.gen_off + (code >> 2)] > 0.f)
         gcap += a.eta[nt.eta_off + (code >> 2)];
     }
+    const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
+    for (int e = e0; e < e1; ++e) lcap += a.eta[nt.eta_off + nt.G + (a.ang[e] >> 1)];
     x[5 * T] = bcap * sc100;
     x[5 * T + 1] = lcap * sc100;
     x[5 * T + 2] = gcap * sc100;
   }
 }
 
-__global__ void k_targets(Args a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, float* Y) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = gid / T;
-  const int t = (int)(gid - row * T);
-  int b = -1;
-  for (int q = 0; q < nb; ++q) {
-    const int s = bscen[q];
-    const int r0 = rowoff[s];
-    if (row >= r0 && row < r0 + a.net[a.scen[s].net].N) {
-      b = q;
-      break;
-    }
-  }
-  if (b < 0) return;
-  const int s = bscen[b];
+__global__ void k_features_nbr(Args a, const int32_t* bscen, const int32_t* rowoff, int T, float* X) {
+  const int s = bscen[blockIdx.y];
   const ScenDev sc = a.scen[s];
   const NetDev nt = a.net[sc.net];
-  const int n = (int)(row - rowoff[s]);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = (int)(gid / T), t = (int)(gid - (int64_t)n * T);
+  if (n >= nt.N) return;
+  const int64_t r0 = rowoff[s];
+  const int64_t row = r0 + n;
+  const int F = 5 * T + 3;
+  float nl = 0.f, nren = 0.f;
+  const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int code = a.ang[e];
+    const int l = code >> 1;
+    const int m = (code & 1) ? a.line_to[nt.line_off + l] : a.line_from[nt.line_off + l];
+    nl += a.load[sc.doff + (int64_t)m * T + t];
+    nren += X[(r0 + m) * F + T + t];
+  }
+  float* x = X + row * F;
+  x[3 * T + t] = nl * 0.01f;
+  x[4 * T + t] = nren;
+}
+
+__global__ void k_targets(Args a, const int32_t* bscen, const int32_t* rowoff, int T, float* Y) {
+  const int s = bscen[blockIdx.y];
+  const ScenDev sc = a.scen[s];
+  const NetDev nt = a.net[sc.net];
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = (int)(gid / T), t = (int)(gid - (int64_t)n * T);
+  if (n >= nt.N) return;
+  const int64_t row = rowoff[s] + n;
   const int64_t TT = T;
   const double pi = a.yhat[sc.yoff + (int64_t)n * TT + t];
   const float th = a.xhat[sc.xoff + (int64_t)(nt.G + nt.L) * TT + (int64_t)n * TT + t];
@@ -1412,17 +1420,20 @@ __global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, con
   }
 }
 
-hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
-                           int64_t rows, float* X, hipStream_t st) {
-  const int64_t n = rows * T;
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, bscen, nb, rowoff, T, X);
+// one grid row per batch entry, (node, hour) along x; maxN = the largest
+// node count in the batch
+hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, int maxN,
+                           float* X, hipStream_t st) {
+  const dim3 grid((unsigned)(((int64_t)maxN * T + 255) / 256), (unsigned)nb);
+  hipLaunchKernelGGL(k_features_own, grid, dim3(256), 0, st, a, bscen, rowoff, T, X);
+  hipLaunchKernelGGL(k_features_nbr, grid, dim3(256), 0, st, a, bscen, rowoff, T, X);
   return hipGetLastError();
 }
 
-hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
-                          int64_t rows, float* Y, hipStream_t st) {
-  const int64_t n = rows * T;
-  hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, bscen, nb, rowoff, T, Y);
+hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, int maxN,
+                          float* Y, hipStream_t st) {
+  const dim3 grid((unsigned)(((int64_t)maxN * T + 255) / 256), (unsigned)nb);
+  hipLaunchKernelGGL(k_targets, grid, dim3(256), 0, st, a, bscen, rowoff, T, Y);
   return hipGetLastError();
 }
 

@@ -28,10 +28,10 @@ hipError_t launch_reset(const Args& a, int bs, int mode, hipStream_t st);
 hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st);
 hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj,
                        hipStream_t st);
-hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
-                           int64_t rows, float* X, hipStream_t st);
-hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T,
-                          int64_t rows, float* Y, hipStream_t st);
+hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, int maxN,
+                           float* X, hipStream_t st);
+hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, int maxN,
+                          float* Y, hipStream_t st);
 hipError_t launch_start(const Args& a, int bs, const int32_t* rowoff, const float* P, hipStream_t st);
 }  // namespace gp
 
@@ -1505,6 +1505,12 @@ int plan_time_sweeps(gp_plan* p, const int32_t* scen, int32_t nb, int32_t iters,
   });
 }
 
+static int max_nodes(const gp_plan* p, const std::vector<int>& batch) {
+  int m = 0;
+  for (int s : batch) m = std::max(m, p->nets[p->scen[s].net].N);
+  return m;
+}
+
 // rows of the learned warm start: one per (listed scenario, node)
 static int64_t nn_layout(gp_plan* p, const std::vector<int>& batch, std::vector<int32_t>& rowoff, int& T) {
   rowoff.assign(p->S, -1);
@@ -1535,6 +1541,7 @@ int plan_nn_rows(gp_plan* p, const int32_t* scen, int32_t nb, int64_t* rows, int
 static void nn_prepare(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, std::vector<int>& batch,
                        int64_t& rows, int& T) {
   check_batch(p, scen, nb, batch);
+  if (nb > 65535) fail(GP_EINVAL, "at most 65535 scenarios per call (one grid row each)");
   std::vector<int32_t> ro;
   rows = nn_layout(p, batch, ro, T);
   if (eta) {
@@ -1557,7 +1564,8 @@ int plan_features(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb
     int64_t rows;
     int T;
     nn_prepare(p, eta, scen, nb, batch, rows, T);
-    HIPCHK(launch_features(make_args(p, 0), p->d_bscen.p, nb, p->d_rowoff.p, T, rows, X_dev, p->stream));
+    HIPCHK(launch_features(make_args(p, 0), p->d_bscen.p, nb, p->d_rowoff.p, T, max_nodes(p, batch), X_dev,
+                           p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
     return GP_OK;
   });
@@ -1573,7 +1581,8 @@ int plan_targets(gp_plan* p, const int32_t* scen, int32_t nb, float* Y_dev) {
     nn_prepare(p, nullptr, scen, nb, batch, rows, T);
     for (int s : batch)
       if (!p->has_solution[s]) fail(GP_ESTATE, "scenario %d has no solution", s);
-    HIPCHK(launch_targets(make_args(p, 0), p->d_bscen.p, nb, p->d_rowoff.p, T, rows, Y_dev, p->stream));
+    HIPCHK(launch_targets(make_args(p, 0), p->d_bscen.p, nb, p->d_rowoff.p, T, max_nodes(p, batch), Y_dev,
+                          p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
     return GP_OK;
   });
