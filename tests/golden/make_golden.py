@@ -70,7 +70,9 @@ def spread(cfg, s):
 
 def spread_draw(cfg, s, k):
     """One draw k of the spread, merged into the stored file under a lock
-    (several draws can run as separate processes)."""
+    (several draws can run as separate processes).  The lock file is left in
+    place: removing it would let a process still waiting on the old file and
+    a newcomer on a fresh one both hold "the" lock."""
     import fcntl
     case = cases.by_id(cfg)
     eta = golden_eta(case)
@@ -95,7 +97,6 @@ def spread_draw(cfg, s, k):
         out["spread_mw"] = SPREAD_MW
         with open(path, "w") as fh:
             json.dump(out, fh)
-    os.remove(path + ".lock")
     print(f"config {cfg} scenario {s} draw {k}: gradient spread so far {out['grad_spread']:.2e}", flush=True)
 
 
