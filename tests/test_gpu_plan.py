@@ -12,7 +12,6 @@ between the marginal cost and the penalty) no solution of that accuracy
 determines the gradient more closely."""
 import json
 import os
-import warnings
 
 import numpy as np
 import pytest
@@ -78,6 +77,15 @@ def _subset20(case, grad):
 
 @pytest.mark.parametrize("cfg,scen", [(1, [0, 1]), (3, [0, 1])])
 def test_full_size_against_stored_oracle(cfg, scen):
+    """Full-size scenarios against stored oracle values: cost, the full
+    gradient and a 20-capacity subset of it at the 1e-4 KKT tolerance.  The
+    subset picks the most congested lines, whose gradient entries follow the
+    line duals; a 1e-4 solve can leave about 1 % in a single such entry
+    (config 3 scenario 1: one line), which the full-vector bar absorbs and a
+    20-entry subset does not.  A subset that misses its bar is therefore
+    solved again to 1e-5 and must meet it there: an error that vanishes as
+    the solve tightens is the solve's accuracy, one that stays is the
+    gradient's."""
     golds = [_golden(cfg, s) for s in scen]
     case = cases.by_id(cfg)
     eta = _golden_eta(case)
@@ -99,20 +107,21 @@ def test_full_size_against_stored_oracle(cfg, scen):
         print(f"[gpu] config {cfg} scenario {s}: grad err {err:.2e} bar {bar:.2e}", flush=True)
         assert err <= bar, (s, err, bar)
         sub = _subset20(case, ref)
-        errs = np.linalg.norm(grads[b][sub] - ref[sub]) / np.linalg.norm(ref[sub])
-        # the same spread measure restricted to the subset, from the stored
+        # the spread measure restricted to the subset, from the stored
         # oracle gradients at the moved capacities
         g0 = np.array(gd["grad"])
         sub_spread = max([np.linalg.norm(np.array(g)[sub] - g0[sub]) / np.linalg.norm(g0[sub])
                           for g in gd.get("spread_grads", [])] or [0.0])
         bar_sub = max(1e-3, sub_spread)
+        errs = np.linalg.norm(grads[b][sub] - ref[sub]) / np.linalg.norm(ref[sub])
         print(f"[gpu] config {cfg} scenario {s}: subset grad err {errs:.2e} bar {bar_sub:.2e}", flush=True)
-        if gd.get("kink") and "spread_grads" not in gd and errs > bar_sub:
-            # the oracle flags a kink here and its spread is not measured yet
-            # (hours of CPU per draw): the subset bar is undecided, not failed
-            warnings.warn(f"config {cfg} scenario {s}: subset error {errs:.2e} at a flagged kink; "
-                          "spread not yet in the golden file")
-            continue
+        if errs > bar_sub:
+            with _plan(case, tol=1e-5, max_iter=2_000_000) as q:
+                _, st5, rc5 = q.solve(eta, [s])
+                assert rc5 == 0, st5
+                g5, _, _ = q.grad([s], omega)
+            errs = np.linalg.norm(g5[sub] - ref[sub]) / np.linalg.norm(ref[sub])
+            print(f"[gpu] config {cfg} scenario {s}: subset grad err at 1e-5 {errs:.2e}", flush=True)
         assert errs <= bar_sub, (s, errs, bar_sub)
 
 
