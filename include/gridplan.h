@@ -71,7 +71,8 @@ typedef struct {
   const double* gen_cost;    /* [n_gens] marginal cost, $/MWh, >= 0 */
   const double* gen_emis;    /* [n_gens] emission rate, t/MWh, >= 0 */
   const int32_t* batt_node;  /* [n_batt] */
-  const double* eta_min;     /* [n_gens + n_lines + n_batt], >= 0 */
+  const double* eta_min;     /* [n_gens + n_lines + n_batt], >= 0; battery
+                                entries > 0 (dispatch_grad) */
   const double* eta_max;     /* [n_gens + n_lines + n_batt], >= eta_min */
 } gp_network;
 
@@ -107,7 +108,8 @@ typedef struct {
   int32_t block;         /* threads per block (64/128/256/512); 0 = tuned */
   int32_t no_graph;      /* 1 = launch eagerly instead of hipGraph replay */
   double rho0;           /* initial primal weight [10] */
-  int32_t verbose;       /* 1 = progress lines on stderr */
+  int32_t verbose;       /* 1 = progress lines on stderr, 2 = also a line
+                            per convergence check of the first batch entry */
   int32_t variant;       /* sweep form: 0 tuned, 1 one block per tile,
                             2 persistent work queue */
   int32_t accept_warm;   /* 1 = take every warm start as given: no
@@ -167,14 +169,28 @@ int dispatch_solve_batch(gp_plan* p, const double* eta, const int32_t* scen, int
  *   (1/nb) sum_s w_s h_s(x*_s(eta)),  h_s = c_s + omega * emissions,
  * with respect to eta, for the scenarios of the last dispatch_solve_batch
  * call (scen must equal that list).  The gamma term is not included.
+ * eta: nullable host [K]; when given it must equal (bitwise) the eta of that
+ * solve, so a caller holding capacities from an earlier solve gets
+ * GP_ESTATE instead of the gradient at other capacities.
+ * At a zero generator or line capacity the value is the derivative for
+ * increasing capacity: -sum_t avail * max(z, 0) for a generator and
+ * -sum_t |z| for a line, z the bound's multiplier E'y - q - r x.
  * For omega > 0 the emission part solves an adjoint QP with the same
  * iteration and stopping triple, the gap measured relative to
  * 1 + max(|P|, |D|, |D(0)|) (its optimum can sit near zero); returns
  * GP_ENOTCONVERGED (gradient written) if it misses opt.tol.
  * grad_out: [K] host FP64.  h_out: nullable, receives the weighted mean
  * planner objective.  Errors: GP_ESTATE when no matching solve exists. */
-int dispatch_grad(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,
-                  double* h_out);
+int dispatch_grad(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, double omega,
+                  double* grad_out, double* h_out);
+
+/* The weighted mean planner objective (1/nb) sum_s w_s (c_s + omega * e_s)
+ * of the last dispatch_solve_batch (eq. (1) without gamma'eta; c_s and the
+ * emissions e_s at each scenario's returned point, FP64), for the same
+ * scenario list and, when eta is given (nullable host [K]), the same
+ * capacities.  h_out: host scalar.  Errors: GP_ESTATE, GP_EINVAL. */
+int dispatch_objective(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, double omega,
+                       double* h_out);
 
 /* One projected gradient step (Section 2.2):
  *   Delta = gamma + dispatch_grad(...),  eta <- clip(eta - alpha*Delta).
@@ -182,7 +198,10 @@ int dispatch_grad(gp_plan* p, const int32_t* scen, int32_t nb, double omega, dou
  * warm-started from their previous solutions when warm_mode = 1.
  * gamma: [K] $/MW-yr.  eta_inout: [K] updated in place.  phi_out: nullable,
  * receives gamma'eta + (1/nb) sum w_s h_s at the input eta.
- * delta_out: nullable [K], receives Delta. */
+ * delta_out: nullable [K], receives Delta.  GP_ENOTCONVERGED: a solve or
+ * the adjoint missed opt.tol; eta_inout still took the step (with the
+ * gradient of the unconverged point), so a caller that wants to discard
+ * such steps keeps a copy of eta. */
 int plan_step(gp_plan* p, double alpha, const int32_t* scen, int32_t nb, const double* gamma,
               double omega, int32_t warm_mode, double* eta_inout, double* phi_out,
               double* delta_out);

@@ -20,6 +20,23 @@ which gives, for a loss l with gradient g = grad h(x*),
 For h = c (no emissions weight) the fit is exact with w = y*, so
 dl/dx_A = -z_A and the gradient is the envelope-theorem value
 -sum_i a_i z_i (z the box multipliers); that identity is a pin.
+
+A capacity at zero collapses its boxes to points (a generator with
+eta_g = 0, a line with eta_l = 0).  The map is then one-sided in eta, and
+the derivative returned is the one for increasing capacity: an entry whose
+multiplier z_i is positive would move to the bound that opens, so it counts
+as held at that bound (the upper one; for a line with z_i < 0 the lower one,
+-eta_l), and an entry with z_i <= 0 stays where it is.
+
+The map x*(eta) is piecewise affine, so the planner objective is piecewise
+quadratic: on every segment of capacities over which the active set stays
+optimal it is a quadratic, and a central difference along such a segment is
+its exact derivative.  ``fixed_set_differences`` evaluates that difference
+by re-solving the equality system of the active set at eta_j +- h (one
+factorisation, two back-solves per capacity) and verifying the optimality
+signs at both ends; a coordinate whose verification fails on either side
+has a kink within h of eta (the survey of the paper's method calls such
+points non-differentiable; Section 2.2 assumes differentiability).
 """
 from __future__ import annotations
 
@@ -31,6 +48,34 @@ from . import dispatch as D
 def loss_gradient_x(qp: D.QP, x: np.ndarray, omega: float) -> np.ndarray:
     """grad h(x) = r x + q + omega * emissions-rate."""
     return qp.r * x + qp.q + omega * qp.emis
+
+
+def _dependent(qp: D.QP):
+    """Entries whose upper / lower bound is a nonzero multiple of a capacity."""
+    dep_hi = (qp.hi_idx >= 0) & (qp.hi_coef != 0)
+    dep_lo = (qp.lo_idx >= 0) & (qp.lo_coef != 0)
+    return dep_hi, dep_lo
+
+
+def _collapsed(qp: D.QP):
+    """Entries whose box is a single point."""
+    return np.isfinite(qp.lo) & np.isfinite(qp.hi) & (qp.hi - qp.lo <= 1e-12 * (1 + np.abs(qp.hi)))
+
+
+def capacity_sides(qp: D.QP, sol: D.Solution):
+    """Active sets used for the derivative (see the module docstring): the
+    solution's own classification, except at boxes collapsed by a zero
+    capacity, where the sign of the multiplier picks the side that opens
+    (a generator with z_i <= 0 stays at its fixed lower bound 0 and
+    contributes nothing)."""
+    at_lo = sol.active_lo.copy()
+    at_hi = sol.active_hi.copy()
+    dep_hi, dep_lo = _dependent(qp)
+    coll = _collapsed(qp) & (dep_hi | dep_lo)
+    up = coll & dep_hi & (sol.z > 0)
+    at_hi[coll] = up[coll]
+    at_lo[coll] = ~up[coll]
+    return at_lo, at_hi
 
 
 def eta_from_active(qp: D.QP, dl_dx: np.ndarray, at_lo: np.ndarray, at_hi: np.ndarray) -> np.ndarray:
@@ -50,8 +95,8 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
     and a flag for points where the map is not differentiable (weakly active
     bounds, or a solution whose active set the polish could not settle; there
     the value is one element of the generalised gradient)."""
-    at_lo, at_hi = sol.active_lo, sol.active_hi
-    free = ~(at_lo | at_hi)
+    at_lo, at_hi = capacity_sides(qp, sol)
+    free = ~(sol.active_lo | sol.active_hi)
     g = loss_gradient_x(qp, sol.x, omega)
     w, rankdef = D.adjoint_lsq(qp, free, g)
     dl_dx = g - qp.E.T @ w
@@ -59,12 +104,75 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
     env = eta_from_active(qp, -sol.z, at_lo, at_hi)
     # weakly active entries whose bound depends on a capacity make the map kinked
     bscale = 1.0 + np.abs(qp.q).max()
-    dep = ((at_hi & (qp.hi_idx >= 0) & (qp.hi_coef != 0)) |
-           (at_lo & (qp.lo_idx >= 0) & (qp.lo_coef != 0)))
-    fixed = np.isfinite(qp.lo) & np.isfinite(qp.hi) & (qp.hi - qp.lo <= 1e-12 * (1 + np.abs(qp.hi)))
-    weak = dep & ~fixed & (np.abs(sol.z) < 1e-7 * bscale)
+    dep_hi, dep_lo = _dependent(qp)
+    dep = (sol.active_hi & dep_hi) | (sol.active_lo & dep_lo)
+    weak = dep & ~_collapsed(qp) & (np.abs(sol.z) < 1e-7 * bscale)
     return dict(grad=grad, envelope=env, w=w, dl_dx=dl_dx, kink=bool(weak.any() or not sol.polished),
                 rank_deficient=rankdef)
+
+
+def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e-3, js=None,
+                          tol_x: float = 1e-9, tol_z: float = 1e-9) -> dict:
+    """Central differences of h_s along each capacity j in ``js`` (default
+    all), from re-solves with the solution's active set held fixed.
+
+    At eta +- h e_j the active entries sit at their moved bounds and the free
+    entries solve  r x_F + q_F = E_F' y,  E_F x_F = e - E_A x_A  (the reduced
+    system does not depend on eta, only its right-hand side does, so one
+    factorisation serves every coordinate).  Each end is accepted only if it
+    is optimal: free entries inside their moved box and every held entry's
+    multiplier with the right sign.  Returns per coordinate the central,
+    forward and backward differences and ``ok`` (both ends verified; then the
+    central difference is the exact derivative of the quadratic piece)."""
+    if not sol.polished:
+        raise ValueError("fixed-active-set differences need a polished solution")
+    K = qp.K
+    js = np.arange(K) if js is None else np.asarray(js)
+    at_lo, at_hi = sol.active_lo, sol.active_hi
+    free = ~(at_lo | at_hi)
+    E = qp.E.tocsc()
+    EF, EA, msolve, _ = D._free_factor(qp, free)
+    EAc = E[:, ~free]
+    x0, z0 = sol.x, sol.z
+    g0 = loss_gradient_x(qp, x0, omega)
+    bscale = 1.0 + np.abs(qp.q).max()
+    xs = 1.0 + max(np.abs(qp.lo[np.isfinite(qp.lo)]).max(initial=0.0),
+                   np.abs(qp.hi[np.isfinite(qp.hi)]).max(initial=0.0))
+    coll = _collapsed(qp)
+    idx_free = np.where(free)[0]
+    out = dict(central=np.zeros(len(js)), forward=np.zeros(len(js)), backward=np.zeros(len(js)),
+               ok=np.zeros(len(js), bool), ok_plus=np.zeros(len(js), bool), ok_minus=np.zeros(len(js), bool))
+    for k, j in enumerate(js):
+        # bound movement per unit capacity (a_i where the bound is a_i eta_j)
+        dhi = np.where(qp.hi_idx == j, qp.hi_coef, 0.0)
+        dlo = np.where(qp.lo_idx == j, qp.lo_coef, 0.0)
+        dxA = np.where(at_hi, dhi, np.where(at_lo, dlo, 0.0))
+        # r dx_F = E_F' dy,  E_F dx_F = -E_A dx_A
+        dy = -qp.r * msolve(EAc @ dxA[~free])
+        dx = dxA.copy()
+        dx[free] = (EF.T @ dy) / qp.r
+        dz = E.T @ dy - qp.r * dx
+        oks = []
+        for sgn in (1.0, -1.0):
+            x = x0 + sgn * h * dx
+            z = z0 + sgn * h * dz
+            lo = qp.lo + sgn * h * dlo
+            hi = qp.hi + sgn * h * dhi
+            inside = np.all((x[idx_free] >= lo[idx_free] - tol_x * xs) & (x[idx_free] <= hi[idx_free] + tol_x * xs))
+            held = ~free & ~coll
+            signs = np.all(z[held & at_hi] >= -tol_z * bscale) and np.all(z[held & at_lo & ~at_hi] <= tol_z * bscale)
+            oks.append(bool(inside and signs))
+        # h(x0 + s h dx) - h(x0) = s h g0'dx + (r/2) h^2 ||dx||^2  (exact for the quadratic)
+        lin = float(g0 @ dx)
+        quad = 0.5 * qp.r * h * h * float(dx @ dx)
+        vp, vm = h * lin + quad, -h * lin + quad
+        out["central"][k] = (vp - vm) / (2 * h)
+        out["forward"][k] = vp / h
+        out["backward"][k] = -vm / h
+        out["ok_plus"][k], out["ok_minus"][k] = oks
+        out["ok"][k] = oks[0] and oks[1]
+    out["js"] = js
+    return out
 
 
 def batch_gradient(case, eta: np.ndarray, scen, omega: float, tol: float = 1e-10):

@@ -9,6 +9,8 @@ solve).  Torch only carries the K-vector between host and device.
 """
 from __future__ import annotations
 
+import warnings
+
 import numpy as np
 import torch
 
@@ -20,10 +22,12 @@ class CapacityCost(torch.autograd.Function):
     def forward(ctx, eta: torch.Tensor, plan: "gridplan.Plan", scen, omega: float = 0.0,
                 warm: int = 0):
         e = eta.detach().to("cpu", torch.float64).numpy().copy()
-        cost, st, _ = plan.solve(e, scen, warm)
-        w = np.array([plan.case.scenarios[s].weight for s in scen])
-        emis = np.array([d["emis"] for d in st])
-        h = float(np.mean(w * (cost + omega * emis)))
+        _, st, rc = plan.solve(e, scen, warm)
+        if rc != gridplan.GP_OK:
+            bad = [s for s, d in zip(scen, st) if d["status"]]
+            warnings.warn(f"dispatch solves of scenarios {bad} missed the tolerance; the objective and its "
+                          "gradient are those of the unconverged points", RuntimeWarning, stacklevel=2)
+        h = plan.objective(scen, omega, eta=e)
         ctx.plan, ctx.scen, ctx.omega, ctx.eta = plan, list(scen), float(omega), e
         return torch.tensor(h, dtype=eta.dtype, device=eta.device)
 
@@ -31,14 +35,15 @@ class CapacityCost(torch.autograd.Function):
     def backward(ctx, gout: torch.Tensor):
         plan = ctx.plan
         try:
-            g, _, _ = plan.grad(ctx.scen, ctx.omega)
+            g, _, _ = plan.grad(ctx.scen, ctx.omega, eta=ctx.eta)
         except gridplan.GridplanError as e:
             if e.code != gridplan.GP_ESTATE:
                 raise
-            # the plan solved another batch since forward: re-solve this one
-            # from its stored solutions, then differentiate
+            # the plan solved another batch or other capacities since
+            # forward: re-solve this one from its stored solutions, then
+            # differentiate
             plan.solve(ctx.eta, ctx.scen, 1)
-            g, _, _ = plan.grad(ctx.scen, ctx.omega)
+            g, _, _ = plan.grad(ctx.scen, ctx.omega, eta=ctx.eta)
         gt = torch.from_numpy(np.ascontiguousarray(g)).to(gout.device, gout.dtype)
         return gout * gt, None, None, None, None
 

@@ -1058,9 +1058,17 @@ __global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb
   if (lane == 0) a.stats[goff[b] + dev] = acc;  // stats buffer reused as gradient output
 }
 
-// Active-bound mask of the forward solution: bit 0 = at lower bound, bit 1
-// = at an upper bound that depends on a capacity.  Entries whose two bounds
-// coincide (zero availability) are marked at their lower bound only.
+// Active-bound mask of the forward solution: bit 0 = held at its lower
+// bound, bit 1 = held at an upper bound that depends on a capacity.  A box
+// collapsed to a point by a zero capacity (a generator with eta_g = 0 and
+// nonzero availability, a line with eta_l = 0) is marked for the derivative
+// with respect to increasing capacity (Section 2.2 at the edge of the
+// capacity box): the side that would open, by the sign of the multiplier
+// z = E'y - q - r x of the forward solution, so that the envelope pass
+// returns -a max(z, 0) for such a generator and -|z| for such a line.  Entries
+// whose two bounds coincide for any capacity (zero availability) are marked
+// at their lower bound only.  Battery capacities are positive (validated on
+// the host).
 template <int BS>
 __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
   const int tix = blockIdx.x;
@@ -1073,23 +1081,31 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
   const int64_t TT = T;
   const int i = tl.start + threadIdx.x;
   const float* xh = a.xhat + sc.xoff;
+  const double* yb = a.yhat + sc.yoff;
   uint8_t* m = mask + sc.xoff;
-  auto mk = [&](int64_t idx, float lo, float hi, bool hi_dep, bool lo_dep) {
+  auto mk = [&](int64_t idx, float hi) {
     const float v = xh[idx];
     uint8_t b = 0;
-    if (v <= lo) b |= 1;
-    if (v >= hi && hi > lo) b |= hi_dep ? 2 : 1;
-    (void)lo_dep;
+    if (v <= 0.f) b |= 1;
+    if (v >= hi && hi > 0.f) b |= 2;
     m[idx] = b;
   };
   switch (tl.cls) {
     case VC_GEN: {
-      const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + i / T];
-      mk(i, 0.f, hi, true, false);
+      const int g = i / T, t = i - g * T;
+      const float av = a.avail[sc.aoff + i], cap = a.eta[nt.eta_off + g];
+      const float hi = av * cap;
+      if (hi > 0.f || av == 0.f) {
+        mk(i, hi);
+      } else {  // zero capacity: upper side when more capacity would be used
+        const int n = a.gen_node[nt.gen_off + g];
+        const double z = yb[(int64_t)n * TT + t] - (double)a.gen_cost[nt.gen_off + g] - (double)a.r * (double)xh[i];
+        m[i] = z > 0.0 ? 2 : 1;
+      }
       break;
     }
     case VC_LINE: {
-      const int l = i / T;
+      const int l = i / T, t = i - l * T;
       const float cap = a.eta[nt.eta_off + nt.G + l];
       const int64_t idx = (int64_t)nt.G * TT + i;
       const float v = xh[idx];
@@ -1097,8 +1113,11 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
       if (cap > 0.f) {
         if (v >= cap) b = 2;
         else if (v <= -cap) b = 1;
-      } else {
-        b = 1;
+      } else {  // zero capacity: the side the flow would take
+        const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+        const double z = yb[(int64_t)to * TT + t] - yb[(int64_t)fr * TT + t] +
+                         yb[(int64_t)nt.N * TT + (int64_t)l * TT + t] - (double)a.r * (double)v;
+        b = z > 0.0 ? 2 : 1;
       }
       m[idx] = b;
       break;
@@ -1114,9 +1133,9 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
       const float cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
       const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
       const int64_t BT = (int64_t)nt.B * TT;
-      mk(base + i, 0.f, cap, true, false);
-      mk(base + BT + i, 0.f, cap, true, false);
-      mk(base + 2 * BT + i, 0.f, a.hours * cap, true, false);
+      mk(base + i, cap);
+      mk(base + BT + i, cap);
+      mk(base + 2 * BT + i, a.hours * cap);
       break;
     }
   }

@@ -131,40 +131,25 @@ struct ScenHost {
 
 }  // namespace
 
-// Restart and weight-adaptation parameters of the driver.  The defaults
-// were chosen by measurement; GP_* environment variables override them for
-// experiments.
+// Restart and weight-adaptation constants of the driver, chosen by
+// measurement on the 240- and 1000-node workloads and the uneven batch.
 struct Tune {
   double bsuff = 0.2;     // restart when the KKT residual fell by this factor
   double bnec = 0.8;      // ... or by this factor and stopped improving
   double art = 0.05;      // ... or the cycle is this fraction of the iterations since the cold start
-  double pw_theta = 0.5;  // smoothing of the primal-weight update
-  // primal-weight rule at a restart: 0 balance the weighted primal and dual
-  // movement; 1 balance r_bal against max(r_dual, r_gap); 3 balance
-  // max(r_bal, r_soc) against r_gap; 4 balance r_bal against
-  // max(r_dual, min(r_gap, r_bal)).  Rule 1 lets a large gap drive the
-  // weight down while the balance residual stalls (the dual then barely
-  // moves and the gap cannot close: cold solves seen stuck at r_bal ~ 0.2);
-  // rule 4 counts the gap only up to the balance residual.
-  int rule = 4;
+  // Primal weight at a restart: balance the balance-row residual against
+  // max(r_dual, min(r_gap, r_bal)).  Balancing against max(r_dual, r_gap)
+  // let a large gap drive the weight down while the balance residual
+  // stalled (the dual then barely moves and the gap cannot close: cold
+  // solves seen stuck at r_bal ~ 0.2); counting the gap only up to the
+  // balance residual fixed them.  The adjoint solve uses the same rule (a
+  // rule balancing the weighted primal and dual movement let adjoint solves
+  // on the 100-node case diverge).
   double gain = 0.25;     // exponent of the residual-balancing update
-  // rule of the adjoint solve (-1: the dispatch rule).  Rule 0 let the
-  // weights swing until adjoint solves on the 100-node case diverged (KKT
-  // growing to 1e6 within the iteration limit); the dispatch rule converges
-  int arule = -1;
-  int flow_rule = 1;      // 1: adapt the flow-class multiplier at restarts
-  int rmetric = 1;        // restart decisions on 0: the max-norm KKT, 1: the 2-norm KKT
-  int stop_norm = 0;      // stopping test on 0: the max-norm KKT, 2: the 2-norm KKT
   double clamp = 10.0;    // largest factor of one weight update
 };
 
-double env_or(const char* k, double v) {
-  const char* e = std::getenv(k);
-  return e ? std::atof(e) : v;
-}
-
 struct gp_plan {
-  int trace = 0;  // GRIDPLAN_TRACE=1: per-check line for the first batch entry
   Tune tune;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -228,6 +213,7 @@ struct gp_plan {
   int graph_mode = -1;
   // solution bookkeeping
   std::vector<int> has_solution;
+  std::vector<double> last_cost, last_emis;  // c_s and emissions at each scenario's last solution
   std::vector<float> last_cw, last_cwf;
   std::vector<int> cold_iters;  // per network: iterations of its last converged cold solve (0 = none yet)
   std::vector<int> solved_batch;
@@ -300,6 +286,12 @@ void validate_case(const gp_case_desc* cs) {
       if (!(n.eta_min[j] >= 0) || !finite(n.eta_min[j]) || !finite(n.eta_max[j]) ||
           n.eta_max[j] < n.eta_min[j])
         fail(GP_EINVAL, "network %d capacity %d: bad box [%g, %g]", k, j, n.eta_min[j], n.eta_max[j]);
+    // at zero storage capacity the derivative for increasing capacity is the
+    // value of an infinitesimal store (an arbitrage problem over the whole
+    // chain), which the envelope pass does not compute
+    for (int j = n.n_gens + n.n_lines; j < Kn; ++j)
+      if (!(n.eta_min[j] > 0))
+        fail(GP_EINVAL, "network %d battery %d: capacity lower bound must be > 0", k, j - n.n_gens - n.n_lines);
   }
   for (int s = 0; s < cs->n_scenarios; ++s) {
     const gp_scenario& sc = cs->scenarios[s];
@@ -325,23 +317,11 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->S = cs->n_scenarios;
   // copy weights of the consensus splitting (see the kernels' header)
   Weights& w = p->w;
-  w.wb = (float)env_or("GP_WB", 1.0);
-  w.wu = (float)env_or("GP_WU", 1.0);
-  w.wf = (float)env_or("GP_WF", 1.0);
-  w.wth = (float)env_or("GP_WTH", 0.1);
-  w.ws = (float)env_or("GP_WS", 1.0);
-  Tune& tn = p->tune;
-  tn.bsuff = env_or("GP_BSUFF", tn.bsuff);
-  tn.bnec = env_or("GP_BNEC", tn.bnec);
-  tn.art = env_or("GP_ART", tn.art);
-  tn.pw_theta = env_or("GP_PWTHETA", tn.pw_theta);
-  tn.rule = (int)env_or("GP_RULE", tn.rule);
-  tn.flow_rule = (int)env_or("GP_FLOWRULE", tn.flow_rule);
-  tn.clamp = env_or("GP_CLAMP", tn.clamp);
-  tn.rmetric = (int)env_or("GP_RMETRIC", tn.rmetric);
-  tn.gain = env_or("GP_GAIN", tn.gain);
-  tn.arule = (int)env_or("GP_ARULE", tn.arule);
-  tn.stop_norm = (int)env_or("GP_NORM", tn.stop_norm);
+  w.wb = 1.f;    // balance copies of generators, battery ch/dis and line ends
+  w.wu = 1.f;    // balance copy of unserved load
+  w.wf = 1.f;    // flow-row copy of the line flow
+  w.wth = 0.1f;  // flow-row copy of an angle, per beta^2
+  w.ws = 1.f;    // SOC-chain copies
   w.sig_flow = 1.f / (1.f / w.wf + 2.f / w.wth);
   w.rho_f = 2.f * w.wb + w.wf;
   w.rho_b = w.wb + w.ws;
@@ -553,10 +533,11 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     int dev = 0, ncu = 256;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    p->qblocks = std::max(1, (int)env_or("GP_QBLOCKS_PER_CU", 8.0)) * std::max(1, ncu);
-    p->qgrab = std::max(1, (int)env_or("GP_QGRAB", (double)p->qgrab));
+    p->qblocks = 8 * std::max(1, ncu);  // resident blocks of the work-queue form: 8 per CU
   }
   p->has_solution.assign(p->S, 0);
+  p->last_cost.assign(p->S, 0.0);
+  p->last_emis.assign(p->S, 0.0);
   p->last_cw.assign(p->S, 0.f);
   p->last_cwf.assign(p->S, 1.f);
   p->cold_iters.assign(p->nets.size(), 0);
@@ -936,8 +917,11 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
     }
   }
   const Tune& tn = p->tune;
-  auto stop_of = [&](const Kkt& k) { return tn.stop_norm == 2 ? k.kkt2 : k.kkt; };
-  auto rmet_of = [&](const Kkt& k) { return tn.rmetric == 1 ? k.kkt2 : k.kkt; };
+  // stop on the max-norm KKT residual (the documented test); restart
+  // decisions follow the same test with relative 2-norms, which moves more
+  // smoothly than a max over rows
+  auto stop_of = [&](const Kkt& k) { return k.kkt; };
+  auto rmet_of = [&](const Kkt& k) { return k.kkt2; };
   const int bs = block_size(p);
   // per scenario: warm when asked for and a stored point exists
   std::vector<int32_t> start(nb, 0);
@@ -1072,33 +1056,21 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       const double m = rmet_of(k);
       const bool go = m <= tn.bsuff * k_restart[b] || (m <= tn.bnec * k_restart[b] && m > k_last[b]) ||
                       inner[b] >= tn.art * since_cold[b];
-      if (p->trace && b == 0)
+      if (p->opt.verbose >= 2 && b == 0)
         fprintf(stderr, "[trace] mode %d it %d kkt %.3e bal %.2e flow %.2e soc %.2e dual %.2e gap %.2e c %.4g cf %.4g dx %.4g dy %.4g restart %d\n",
                 mode, total[b], k.kkt, k.r_bal, k.r_flow, k.r_soc, k.r_dual, k.r_gap, (double)p->h_cw[s],
                 (double)p->h_cwf[s], std::sqrt(st[ST_DX2]), std::sqrt(st[ST_DY2]), (int)go);
       k_last[b] = m;
       if (go) {
-        const double dx = std::sqrt(st[ST_DX2]), dy = std::sqrt(st[ST_DY2]);
         const double c = p->h_cw[s];
-        double cn = c;
-        const int rule = (mode == 1 && tn.arule >= 0) ? tn.arule : tn.rule;
-        if (rule == 0) {
-          if (dx > 1e-12 && dy > 1e-12 && std::isfinite(dx) && std::isfinite(dy))
-            cn = std::exp(tn.pw_theta * std::log(dy / dx) + (1.0 - tn.pw_theta) * std::log(c));
-        } else {
-          const double num = rule == 3 ? std::max(k.r_bal, k.r_soc) : k.r_bal;
-          const double den = rule == 3   ? k.r_gap
-                             : rule == 4 ? std::max(k.r_dual, std::min(k.r_gap, k.r_bal))
-                                         : std::max(k.r_dual, k.r_gap);
-          const double f = std::pow(std::max(num, 1e-16) / std::max(den, 1e-16), tn.gain);
-          cn = c * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
-        }
+        const double num = k.r_bal, den = std::max(k.r_dual, std::min(k.r_gap, k.r_bal));
+        const double f = std::pow(std::max(num, 1e-16) / std::max(den, 1e-16), tn.gain);
+        const double cn = c * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
         p->h_cw[s] = (float)std::min(std::max(cn, 1e-6), 1e8);
-        if (tn.flow_rule == 1) {
-          const double f = std::pow(std::max(k.r_flow, 1e-16) / std::max(k.r_dual, 1e-16), tn.gain);
-          const double m = p->h_cwf[s] * std::min(std::max(f, 1.0 / tn.clamp), tn.clamp);
-          p->h_cwf[s] = (float)std::min(std::max(m, 1e-4), 1e4);
-        }
+        // flow-class multiplier: balance the flow rows against stationarity
+        const double ff = std::pow(std::max(k.r_flow, 1e-16) / std::max(k.r_dual, 1e-16), tn.gain);
+        const double mf = p->h_cwf[s] * std::min(std::max(ff, 1.0 / tn.clamp), tn.clamp);
+        p->h_cwf[s] = (float)std::min(std::max(mf, 1e-4), 1e4);
         p->h_restart[s] = 1;
         any_restart = true;
         inner[b] = 0;
@@ -1220,6 +1192,8 @@ int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, i
   const int rem = iterate(p, 0, einf, warm, st, 0.0);
   for (int b = 0; b < nb; ++b) {
     p->has_solution[batch[b]] = 1;
+    p->last_cost[batch[b]] = st[b].cost;
+    p->last_emis[batch[b]] = st[b].emis;
     if (cost_out) cost_out[b] = st[b].cost;
     if (stats_out) stats_out[b] = st[b];
   }
@@ -1228,13 +1202,23 @@ int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, i
   return rem ? GP_ENOTCONVERGED : GP_OK;
 }
 
-int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,
+void check_last_solve(const gp_plan* p, const std::vector<int>& batch, const double* eta, const char* who) {
+  if (batch != p->solved_batch)
+    fail(GP_ESTATE, "%s needs a dispatch_solve_batch on the same scenario list first", who);
+  if (eta)
+    for (int64_t j = 0; j < p->K; ++j)
+      if (!(eta[j] == p->eta_last[j]))
+        fail(GP_ESTATE, "%s: eta[%lld] = %.17g differs from the last solve's %.17g", who, (long long)j, eta[j],
+             p->eta_last[j]);
+}
+
+int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, double omega, double* grad_out,
               double* h_out) {
   std::vector<int> batch;
   check_batch(p, scen, nb, batch);
   if (!grad_out) fail(GP_EINVAL, "grad_out is NULL");
   if (!std::isfinite(omega) || omega < 0) fail(GP_EINVAL, "omega must be finite and >= 0");
-  if (batch != p->solved_batch) fail(GP_ESTATE, "dispatch_grad needs a dispatch_solve_batch on the same scenario list first");
+  check_last_solve(p, batch, eta, "dispatch_grad");
   build_tiles(p, batch);
   hipStream_t st = p->stream;
   // objective parts of the forward solution
@@ -1346,7 +1330,6 @@ int plan_init(gp_plan** out, const gp_case_desc* cs, const gp_options* opt, void
     }
     p = new gp_plan();
     if (opt) p->opt = *opt;
-    if (const char* e = std::getenv("GRIDPLAN_TRACE")) p->trace = std::atoi(e);
     if (hip_stream) {
       p->stream = (hipStream_t)hip_stream;
     } else {
@@ -1378,10 +1361,27 @@ int dispatch_solve_batch(gp_plan* p, const double* eta, const int32_t* scen, int
   return guarded(p, [&] { return solve_impl(p, eta, scen, nb, warm_mode, cost_out, stats_out); });
 }
 
-int dispatch_grad(gp_plan* p, const int32_t* scen, int32_t nb, double omega, double* grad_out,
-                  double* h_out) {
+int dispatch_grad(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, double omega,
+                  double* grad_out, double* h_out) {
   if (!p) return GP_EINVAL;
-  return guarded(p, [&] { return grad_impl(p, scen, nb, omega, grad_out, h_out); });
+  return guarded(p, [&] { return grad_impl(p, scen, nb, eta, omega, grad_out, h_out); });
+}
+
+int dispatch_objective(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, double omega,
+                       double* h_out) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    std::vector<int> batch;
+    check_batch(p, scen, nb, batch);
+    if (!h_out) fail(GP_EINVAL, "h_out is NULL");
+    if (!std::isfinite(omega) || omega < 0) fail(GP_EINVAL, "omega must be finite and >= 0");
+    check_last_solve(p, batch, eta, "dispatch_objective");
+    // (1/nb) sum_s w_s (c_s + omega emis_s), fixed summation order
+    double h = 0.0;
+    for (int s : batch) h += p->scen[s].weight * (p->last_cost[s] + omega * p->last_emis[s]) / nb;
+    *h_out = h;
+    return GP_OK;
+  });
 }
 
 int plan_step(gp_plan* p, double alpha, const int32_t* scen, int32_t nb, const double* gamma,
@@ -1396,7 +1396,7 @@ int plan_step(gp_plan* p, double alpha, const int32_t* scen, int32_t nb, const d
     const int rc1 = solve_impl(p, eta_inout, scen, nb, warm_mode, nullptr, nullptr);
     std::vector<double> g(p->K);
     double h = 0.0;
-    const int rc2 = grad_impl(p, scen, nb, omega, g.data(), &h);
+    const int rc2 = grad_impl(p, scen, nb, nullptr, omega, g.data(), &h);
     double phi = h;
     for (int64_t j = 0; j < p->K; ++j) phi += gamma[j] * eta_inout[j];
     for (const NetHost& n : p->nets) {

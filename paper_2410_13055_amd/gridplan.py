@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgridplan.so")
 GP_OK, GP_ENOTCONVERGED = 0, 1
 GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ESTATE = -1, -2, -3, -4
 
-EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "plan_step",
+EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "dispatch_objective", "plan_step",
            "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_tuning",
            "plan_nn_rows", "plan_features", "plan_targets", "plan_start_from_prediction",
            "mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
@@ -94,9 +94,12 @@ def load(path: str = LIB_PATH):
     lib.dispatch_solve_batch.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32,
                                          C.c_int32, P(C.c_double), P(gp_solve_stats)]
     lib.dispatch_solve_batch.restype = C.c_int
-    lib.dispatch_grad.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_double,
+    lib.dispatch_grad.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32, C.c_double,
                                   P(C.c_double), P(C.c_double)]
     lib.dispatch_grad.restype = C.c_int
+    lib.dispatch_objective.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32, C.c_double,
+                                       P(C.c_double)]
+    lib.dispatch_objective.restype = C.c_int
     lib.plan_step.argtypes = [C.c_void_p, C.c_double, P(C.c_int32), C.c_int32, P(C.c_double),
                               C.c_double, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.plan_step.restype = C.c_int
@@ -273,15 +276,27 @@ class Plan:
         self._check(rc)
         return cost, [st[i].as_dict() for i in range(nb)], rc
 
-    def grad(self, scen, omega: float = 0.0):
-        """dispatch_grad: returns (grad[K], weighted mean h, rc)."""
+    def grad(self, scen, omega: float = 0.0, eta=None):
+        """dispatch_grad: returns (grad[K], weighted mean h, rc).  With eta
+        given, the library checks that it is the last solve's."""
         idx = self._idx(scen)
+        e = None if eta is None else np.ascontiguousarray(eta, np.float64)
         g = np.zeros(max(self.K, 1))
         h = C.c_double()
-        rc = self.lib.dispatch_grad(self.h, _ptr(idx, C.c_int32), idx.shape[0], float(omega),
-                                    _ptr(g, C.c_double), C.byref(h))
+        rc = self.lib.dispatch_grad(self.h, _ptr(e, C.c_double), _ptr(idx, C.c_int32), idx.shape[0],
+                                    float(omega), _ptr(g, C.c_double), C.byref(h))
         self._check(rc)
         return g[:self.K], float(h.value), rc
+
+    def objective(self, scen, omega: float = 0.0, eta=None):
+        """dispatch_objective: the weighted mean planner objective of the
+        last solve of ``scen`` (at ``eta`` when given)."""
+        idx = self._idx(scen)
+        e = None if eta is None else np.ascontiguousarray(eta, np.float64)
+        h = C.c_double()
+        self._check(self.lib.dispatch_objective(self.h, _ptr(e, C.c_double), _ptr(idx, C.c_int32),
+                                                idx.shape[0], float(omega), C.byref(h)), allow_nc=False)
+        return float(h.value)
 
     def step(self, alpha, scen, gamma, eta, omega: float = 0.0, warm: int = 1):
         """plan_step: returns (new eta, phi at the input eta, Delta, rc)."""

@@ -64,6 +64,7 @@ def _init(case, opts=None):
     (lambda c: setattr(c, "r", 0.0), "regulariser"),
     (lambda c: setattr(c, "eff", 1.5), "eff"),
     (lambda c: setattr(c.scenarios[0], "network", 3), "network"),
+    (lambda c: c.networks[0].eta_min.__setitem__(-1, 0.0), "battery 1: capacity lower bound"),
 ])
 def test_plan_init_rejects_bad_case(mutate, needle):
     cs = cases.config0()
@@ -93,7 +94,8 @@ def test_null_arguments():
     assert lib.plan_init(C.byref(h), None, None, None) == gpb.GP_EINVAL
     assert b"NULL" in lib.plan_last_error(None)
     assert lib.dispatch_solve_batch(None, None, None, 0, 0, None, None) == gpb.GP_EINVAL
-    assert lib.dispatch_grad(None, None, 0, 0.0, None, None) == gpb.GP_EINVAL
+    assert lib.dispatch_grad(None, None, None, 0, 0.0, None, None) == gpb.GP_EINVAL
+    assert lib.dispatch_objective(None, None, None, 0, 0.0, None) == gpb.GP_EINVAL
     lib.plan_free(None)
 
 
