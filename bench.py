@@ -1,14 +1,18 @@
 #!/usr/bin/env python
 """Benchmark of the batched dispatch hot path on one GPU.
 
-A step is one pass of the hot path over a batch of synthetic scenarios:
-every scenario's economic-dispatch QP solved from a cold start to a relative
-KKT residual of 1e-4 (FP64 check), then the implicit capacity gradient.
-The printed value is scenario-hours per second over the timed steps.
-
-The JSON line also carries the roofline of the dominant sweep kernel
-(algorithmic bytes per launch over its HIP-event duration) and the FP64 CPU
-oracle timed on a bounded sample of the same workload on the host cores.
+Default (the headline): the 1000-node workload (1000 nodes, 1500 lines,
+5000 generators, 500 batteries, T = 168, 128 scenarios).  A step is one
+projected-gradient planning step (Section 2.2) on a batch of scenarios
+sampled from a pool: every scenario's dispatch QP solved from a cold start
+to a relative KKT residual of 1e-4 (FP64 check), the implicit capacity
+gradient, and the projected update.  The printed value is scenario-hours per
+second over the timed steps (converged scenarios only).  Beside it: s/step
+of the cold, previous-iterate and learned warm-start arms on the same
+held-out planning run (network trained outside the timed region on planning
+runs at other storage costs), the roofline of one ADMM iteration (the two
+sweep kernels) against the HBM peak with the survey's algorithmic bytes, and
+the FP64 CPU oracle timed on the host cores.
 """
 import argparse
 import hashlib
@@ -51,6 +55,22 @@ def algorithmic_bytes(case, scen):
     return dict(primal=12 * nx + 8 * ny + 4 * gt, dual=4 * nx + 32 * ny + 4 * nt, n_x=nx, n_y=ny)
 
 
+def sec8d_bytes(case, scen):
+    """Algorithmic bytes of one ADMM iteration (what the method must move,
+    not this design's layout): read and write every FP32 primal (8 n_x),
+    every FP32 dual (8 n_eq), and read every time-varying FP32 parameter
+    (4 (G + N) T for availability and load)."""
+    tot = 0
+    for s in scen:
+        sc = case.scenarios[s]
+        n = case.networks[sc.network]
+        T = sc.T
+        nx = (n.n_gens + n.n_lines + 2 * n.n_nodes + 3 * n.n_batt) * T
+        ny = (n.n_nodes + n.n_lines + n.n_batt) * T
+        tot += 8 * nx + 8 * ny + 4 * (n.n_gens + n.n_nodes) * T
+    return tot
+
+
 def _read_traffic_table():
     path = os.path.join(ROOT, "profiles", "traffic.md")
     tab = {}
@@ -81,34 +101,69 @@ def measured_traffic(kernel, block, workload_id):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(case, hours=24):
-    """The FP64 oracle (interior point to 1e-10, polish, adjoint gradient) on
-    the first `hours` hours of scenario 0, single-threaded BLAS."""
-    import numpy as np
+def _oracle_slice(sub):
+    """One worker of the CPU baseline: the FP64 oracle interior point on one
+    scenario slice (single-threaded BLAS), tracking the solver-independent
+    KKT residual per iterate; returns (hours, seconds to the oracle's 1e-10,
+    seconds to the first iterate at 1e-4 or None, iterations)."""
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
     from threadpoolctl import threadpool_limits
 
-    from paper_2410_13055_amd import cases as C
     from oracle import dispatch as D
-    from oracle import gradient as Gm
 
-    sc = case.scenarios[0]
-    h = min(hours, sc.T)
-    sub = C.Case(name=case.name + f"-first{h}h", networks=case.networks,
-                 scenarios=[C.Scenario(network=sc.network, T=h, avail=sc.avail[:, :h].copy(),
-                                       load=sc.load[:, :h].copy(), weight=8760.0 / h)],
-                 r=case.r, lambda_u=case.lambda_u, eff=case.eff, hours=case.hours, omega=case.omega)
-    off = case.eta_offsets()
-    eta = case.eta_min()[off[sc.network]:off[sc.network + 1]]
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        qp = D.assemble(sub, 0, eta)
-        sol = D.solve(qp)
-        Gm.scenario_gradient(qp, sol, case.omega)
+        qp = D.assemble(sub, 0, sub.eta_min())
+        t_asm = time.perf_counter() - t0
+        sol = D.solve_ipm(qp, track=True)
         dt = time.perf_counter() - t0
-    return {"value": h / dt, "unit": "scenario-hours/s", "cores": 1, "kind": "oracle",
-            "sample": f"scenario 0 of the same workload cut to its first {h} hours "
-                      f"(FP64 interior point to 1e-10 + active-set polish + adjoint gradient), "
-                      f"{dt:.1f} s"}
+    t4 = next((t for k, t in sol.history if k <= 1e-4), None)
+    return sub.scenarios[0].T, dt, (None if t4 is None else t4 + t_asm), sol.iters
+
+
+def cpu_baseline(case, hours=8, n_jobs=None):
+    """The FP64 oracle as it stands, on the host cores: one single-threaded
+    interior-point solve per process over a pool spanning every core the
+    process may use, each on the first `hours` hours of a different scenario
+    of the workload (capacities at their lower bounds).  The solves run side
+    by side, so scenario-hours/s = (sum of hours) / the slowest worker's
+    time, to the oracle's own 1e-10 and to the first iterate whose KKT
+    residual reaches 1e-4."""
+    import multiprocessing as mp
+
+    from paper_2410_13055_amd import cases as C
+
+    cores = len(os.sched_getaffinity(0))
+    n = min(n_jobs or cores, len(case.scenarios))
+    subs = []
+    for s in range(n):
+        sc = case.scenarios[s]
+        h = min(hours, sc.T)
+        subs.append(C.Case(name=case.name + f"-s{s}-first{h}h", networks=[case.networks[sc.network]],
+                           scenarios=[C.Scenario(network=0, T=h, avail=sc.avail[:, :h].copy(),
+                                                 load=sc.load[:, :h].copy(), weight=8760.0 / h)],
+                           r=case.r, lambda_u=case.lambda_u, eff=case.eff, hours=case.hours, omega=case.omega))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(processes=min(cores, n)) as pool:
+        res = pool.map(_oracle_slice, subs, chunksize=1)
+    wall = time.perf_counter() - t0
+    tot_h = sum(r[0] for r in res)
+    worst10 = max(r[1] for r in res)
+    t4s = [r[2] for r in res if r[2] is not None]
+    worst4 = max(t4s) if len(t4s) == len(res) else None
+    return {"value": round(tot_h / worst10, 3), "unit": "scenario-hours/s", "cores": min(cores, n),
+            "kind": "oracle",
+            "to_1e-4": {"scenario_hours_per_s": round(tot_h / worst4, 3) if worst4 else None,
+                        "slowest_worker_s": round(worst4, 2) if worst4 else None},
+            "to_1e-10": {"scenario_hours_per_s": round(tot_h / worst10, 3), "slowest_worker_s": round(worst10, 2)},
+            "pool_wall_s": round(wall, 2),
+            "sample": f"the first {hours} hours of scenarios 0..{n - 1} of the same workload at the capacities' lower "
+                      f"bounds, one FP64 interior-point solve (KKT residual tracked per iterate) per process on "
+                      f"{min(cores, n)} host cores; {tot_h} scenario-hours; value over the slowest worker's solve "
+                      f"time to 1e-10 (the pool's wall time, process start-up included, is pool_wall_s)",
+            "iterations": [r[3] for r in res]}
 
 
 def summarize(stats_csv, pmc_runs, workload_id, commands):
@@ -628,14 +683,210 @@ def warm_start_leg(args):
     print(json.dumps(out), flush=True)
 
 
+def headline_leg(args):
+    """The headline line on the 1000-node workload (see the module
+    docstring).  Projected SGD as in Section 3.2: a pool of scenarios, a
+    batch of B sampled per step, step alpha; the held-out planning run uses
+    a storage capital cost of 250 $/kWh.
+
+    Timed: K cold planning steps.  Untimed beside them (while the run's time
+    budget allows): the previous-iterate and learned warm-start arms on the
+    first M steps of the same batch sequence, the network trained on
+    planning runs at other storage costs, the sweep roofline, the network's
+    MFMA roofline and the CPU oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2410_13055_amd import cases, gridplan
+    from paper_2410_13055_amd.warmstart import LearnedWarmStart
+
+    t_start = time.perf_counter()
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+    case = cases.config4()
+    net = case.networks[0]
+    G, L, N, T = net.n_gens, net.n_lines, net.n_nodes, case.scenarios[0].T
+    pool, B = list(range(args.pool)), args.batch
+    lo, hi = case.eta_min(), case.eta_max()
+    log(f"{WORKLOADS[4]}: case built in {time.perf_counter() - t_start:.1f} s")
+
+    def gamma_for(price):
+        g = case.gamma().copy()
+        g[G + L:] = cases.storage_gamma_per_mw(price)
+        return g
+
+    def batches(seed, n):
+        rng = np.random.default_rng(seed)
+        return [sorted(rng.choice(pool, B, replace=False).tolist()) for _ in range(n)]
+
+    probe = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
+    probe.solve(lo, pool[:B])
+    tb, tv, tce, _ = probe.tuning()
+    probe.close()
+    opts = dict(block=tb, variant=tv, check_every=tce)
+    log(f"sweep configuration: block {tb}, form {tv}, {tce} iterations per replay")
+    plan = gridplan.Plan(case, gridplan.options(**opts), stream=gridplan.current_stream())
+    held = args.ws_held_price
+    gam = gamma_for(held)
+    state = {"alpha": None}
+
+    def step(p, eta, scen, arm, ws=None, collect=None):
+        if arm == "learned":
+            ws.seed(eta, scen)
+        _, st, rc = p.solve(eta, scen, warm=0 if arm == "cold" else 1)
+        g, _, rc2 = p.grad(scen, eta=eta)
+        if collect is not None:
+            collect.collect(eta, scen)
+        if state["alpha"] is None:  # step size of the survey's reading, from the first gradient
+            state["alpha"] = 0.05 * float((hi - lo).min()) / float(np.abs(gam + g).max())
+        return np.clip(eta - state["alpha"] * (gam + g), lo, hi), st, rc, rc2
+
+    def run_arm(p, arm, bl, price=None, ws=None, collect=None, label=""):
+        eta = lo.copy()
+        out = {"s": [], "iters": [], "starts": [], "unconverged": 0, "kkt": []}
+        for k, scen in enumerate(bl):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eta, st, rc, rc2 = step(p, eta, scen, arm, ws, collect)
+            torch.cuda.synchronize()
+            out["s"].append(time.perf_counter() - t0)
+            out["iters"].append(max(x["iters"] for x in st))
+            out["starts"] += [x["start"] for x in st]
+            out["unconverged"] += sum(1 for x in st if x["status"])
+            out["kkt"].append(max(x["kkt"] for x in st))
+            log(f"{label or arm} step {k}: {out['s'][-1]:.2f} s, iterations {out['iters'][-1]}, "
+                f"starts {[x['start'] for x in st]}")
+        out["eta"] = eta
+        return out
+
+    # warm-up: W cold steps of another batch sequence
+    run_arm(plan, "cold", batches(7, args.warmup), label="warmup")
+    torch.cuda.synchronize()
+    # timed: K cold steps of the held-out run
+    held_batches = batches(999, args.steps)
+    t0 = time.perf_counter()
+    cold = run_arm(plan, "cold", held_batches, label="cold (timed)")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    conv_h = args.steps * B * T - cold["unconverged"] * T
+    value = conv_h / elapsed
+    log(f"timed {args.steps} steps in {elapsed:.1f} s: {value:.1f} scenario-hours/s")
+
+    def left():
+        return args.budget - (time.perf_counter() - t_start)
+
+    per_step = elapsed / args.steps
+    M = min(args.arm_steps, args.steps)
+    arms = {"cold": cold}
+    training = None
+    roof_mlp = None
+    # training data (previous-iterate planning runs at other storage costs),
+    # then the two warm arms; each piece runs only while the budget allows it
+    need_collect = len(args.ws_train_prices) * M * per_step * 1.1
+    if left() > need_collect + 2 * M * per_step + 60:
+        ws = LearnedWarmStart(plan, T, seed=0)
+        t1 = time.perf_counter()
+        for i, price in enumerate(args.ws_train_prices):
+            gam_keep = gam
+            gam = gamma_for(price)
+            run_arm(plan, "previous", batches(100 + i, M), collect=ws, label=f"collect {price}")
+            gam = gam_keep
+        collect_s = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        losses = ws.train(epochs=args.ws_epochs, batch_rows=4096, lr=1e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t1
+        training = {"storage_costs": args.ws_train_prices, "steps_per_run": M, "batch": B, "rows": ws.rows,
+                    "epochs": args.ws_epochs, "loss_first": losses[0], "loss_last": losses[-1],
+                    "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
+                    "network": f"{5 * T + 3} -> 512 x3 -> {2 * T}, {ws.net.n_params} parameters"}
+        log(f"trained on {ws.rows} rows in {train_s:.1f} s: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+        if left() > 2 * M * per_step + 30:
+            prev_plan = gridplan.Plan(case, gridplan.options(**opts), stream=gridplan.current_stream())
+            arms["previous"] = run_arm(prev_plan, "previous", held_batches[:M])
+            prev_plan.close()
+            arms["learned"] = run_arm(plan, "learned", held_batches[:M], ws=ws)
+        roof_mlp = mlp_roofline(plan, case, ws.net)
+    plan.close()
+
+    # one ADMM iteration against the HBM peak: 16 scenarios (a GPU's share of
+    # 128 on 8 GPUs; 3 GB resident, far above the 256 MB Infinity Cache)
+    scen16 = list(range(16))
+    p16 = gridplan.Plan(case, gridplan.options(max_iter=64), stream=gridplan.current_stream())
+    p16.solve(lo, scen16)
+    md, mp_ = p16.time_sweeps(scen16, args.sweep_iters)
+    tb16, tv16, _, _ = p16.tuning()
+    p16.close()
+    ab = algorithmic_bytes(case, scen16)
+    b8d = sec8d_bytes(case, scen16)
+    it_ms = md + mp_
+    achieved = b8d / (it_ms * 1e-3) / 1e9
+    sfx = "_q" if tv16 == 2 else ""
+    tp = measured_traffic("k_primal" + sfx, tb16, 4)
+    td = measured_traffic("k_dual" + sfx, tb16, 4)
+    roof = {"bound": "hbm", "kernel": f"k_dual{sfx} + k_primal{sfx} (one ADMM iteration)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (tp + td) if (tp is not None and td is not None) else None,
+            "bytes_per_iteration": b8d, "design_bytes_per_iteration": ab["primal"] + ab["dual"],
+            "ms_per_iteration": round(it_ms, 5), "ms_dual": round(md, 5), "ms_primal": round(mp_, 5),
+            "launch": {"scenarios": 16, "block": tb16, "form": "work queue" if tv16 == 2 else "tile grid"}}
+
+    def med(a, n=None):
+        v = a["s"][:n] if n else a["s"]
+        return round(float(np.median(v)), 4)
+
+    arm_out = {k: {"s_per_step_median": med(v, M), "s_per_step": [round(x, 3) for x in v["s"][:M]],
+                   "iterations_max_per_step": v["iters"][:M],
+                   "starts": {str(q): v["starts"][:M * B].count(q) for q in sorted(set(v["starts"][:M * B]))},
+                   "unconverged": v["unconverged"]} for k, v in arms.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "scenario-hours/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[4] + f"; cold planning steps on batches of {B} sampled from the first "
+                               f"{len(pool)} scenarios; storage cost {held} $/kWh",
+                   "batch": B, "pool": len(pool), "scenario_hours_per_step": B * T, "start": "cold", "tol": 1e-4},
+        "roofline": roof,
+        "s_per_gradient_step": {"first_steps": M, "arms": arm_out,
+                                "speedup_cold_over_learned": (round(med(cold, M) / arm_out["learned"]["s_per_step_median"], 3)
+                                                              if "learned" in arm_out else None),
+                                "speedup_cold_over_previous": (round(med(cold, M) / arm_out["previous"]["s_per_step_median"], 3)
+                                                               if "previous" in arm_out else None),
+                                "training": training},
+        "extra": {"cold_s_per_step_median": med(cold), "iters_max": int(max(cold["iters"])),
+                  "kkt_max": float(max(cold["kkt"])), "unconverged_scenarios": cold["unconverged"],
+                  "mlp_roofline": roof_mlp},
+    }
+    if args.cpu and left() > 60:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_hours)
+    log(f"total {time.perf_counter() - t_start:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-hours", type=int, default=24)
+    ap.add_argument("--config", type=int, default=4, choices=sorted(WORKLOADS),
+                    help="4 (default): the headline line; others: cold solves of every scenario per step")
+    ap.add_argument("--no-cpu", dest="cpu", action="store_false", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-hours", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=4, help="scenarios per planning step (headline)")
+    ap.add_argument("--pool", type=int, default=16, help="scenarios the batches are drawn from (headline)")
+    ap.add_argument("--arm-steps", type=int, default=6, help="steps of the warm-start arms (headline)")
+    ap.add_argument("--budget", type=float, default=500.0,
+                    help="seconds after which the headline run skips its untimed extras")
     ap.add_argument("--sweep-iters", type=int, default=50)
     ap.add_argument("--pmc-block", type=int, default=256, choices=[128, 256, 512],
                     help="block size of the sweeps in --pmc-run")
@@ -659,7 +910,7 @@ def main():
     ap.add_argument("--ws-batch", type=int, default=4)
     ap.add_argument("--ws-steps", type=int, default=6)
     ap.add_argument("--ws-epochs", type=int, default=150)
-    ap.add_argument("--ws-train-prices", type=float, nargs="+", default=[100.0, 175.0, 325.0, 400.0])
+    ap.add_argument("--ws-train-prices", type=float, nargs="+", default=[100.0, 400.0])
     ap.add_argument("--ws-held-price", type=float, default=250.0)
     ap.add_argument("--summarize", metavar="DIR",
                     help="write profiles/sweeps_geo240.md and profiles/traffic.md from the rocprofv3 outputs "
@@ -699,6 +950,9 @@ def main():
         return
     if args.plan_warm:
         plan_warm_leg(args)
+        return
+    if args.config == 4:
+        headline_leg(args)
         return
     case = cases.by_id(args.config)
     scen = list(range(len(case.scenarios)))
@@ -792,7 +1046,7 @@ def main():
     }
     if args.hbm_case:
         out["extra"]["hbm_case"] = hbm_case_sweeps(args.sweep_iters)
-    if not args.no_cpu:
+    if args.cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_hours)
     print(json.dumps(out), flush=True)

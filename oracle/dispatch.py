@@ -43,6 +43,7 @@ E H^-1 E', factorised with SuperLU.
 from __future__ import annotations
 
 import dataclasses
+import time
 from typing import Optional
 
 import numpy as np
@@ -266,7 +267,7 @@ class Solution:
     obj: float
     iters: int
     status: str
-    history: list             # per-iteration KKT residual of the iterate
+    history: list             # per-iteration (KKT residual, seconds) of the iterate when tracked
     polished: bool = False
     degenerate: bool = False  # weakly active bounds or rank-deficient E_F
     active_lo: Optional[np.ndarray] = None
@@ -287,7 +288,10 @@ def solve_ipm(qp: QP, tol: float = 1e-10, max_iter: int = 200, track: bool = Fal
     lo <= x <= hi, with Q = diag(qdiag) (default r I).  Entries with
     lo == hi are fixed and eliminated; free and one-sided bounds are
     allowed.  ``track`` records the solver-independent KKT residual of each
-    iterate (used to time when 1e-4 is first reached)."""
+    iterate and the wall time (perf_counter) at which it was reached, as
+    (kkt, seconds since the start) pairs (used to time when 1e-4 is first
+    reached)."""
+    t_start = time.perf_counter()
     n, m = qp.n, qp.m
     Qd = np.full(n, qp.r) if qdiag is None else np.asarray(qdiag, np.float64)
     fixed = np.isfinite(qp.lo) & np.isfinite(qp.hi) & (qp.hi - qp.lo <= 1e-12 * (1 + np.abs(qp.hi)))
@@ -330,7 +334,7 @@ def solve_ipm(qp: QP, tol: float = 1e-10, max_iter: int = 200, track: bool = Fal
         if track:
             xf = np.where(fixed, qp.lo, 0.0)
             xf[act] = x
-            hist.append(kkt_residual(qp, xf, y)["kkt"])
+            hist.append((kkt_residual(qp, xf, y)["kkt"], time.perf_counter() - t_start))
         if (np.abs(rp).max(initial=0.0) / enorm < tol and np.abs(rd).max(initial=0.0) / qnorm < tol
                 and mu * max(nb, 1) / (1.0 + abs(P)) < tol):
             status = "optimal"

@@ -123,7 +123,11 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
     is optimal: free entries inside their moved box and every held entry's
     multiplier with the right sign.  Returns per coordinate the central,
     forward and backward differences and ``ok`` (both ends verified; then the
-    central difference is the exact derivative of the quadratic piece)."""
+    central difference is the exact derivative of the quadratic piece), the
+    distance to the nearest kink along the coordinate (``dist``: the largest
+    step, either way, for which the active set stays optimal, from a ratio
+    test on the step direction) and the curvature of h along it
+    (``curv`` = d2h/deta_j2 on the piece)."""
     if not sol.polished:
         raise ValueError("fixed-active-set differences need a polished solution")
     K = qp.K
@@ -141,7 +145,16 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
     coll = _collapsed(qp)
     idx_free = np.where(free)[0]
     out = dict(central=np.zeros(len(js)), forward=np.zeros(len(js)), backward=np.zeros(len(js)),
-               ok=np.zeros(len(js), bool), ok_plus=np.zeros(len(js), bool), ok_minus=np.zeros(len(js), bool))
+               ok=np.zeros(len(js), bool), ok_plus=np.zeros(len(js), bool), ok_minus=np.zeros(len(js), bool),
+               dist=np.zeros(len(js)), curv=np.zeros(len(js)))
+    held_hi = ~free & ~coll & at_hi
+    held_lo = ~free & ~coll & at_lo & ~at_hi
+    fin_lo, fin_hi = np.isfinite(qp.lo), np.isfinite(qp.hi)
+
+    def ratio(num, den):
+        """min over den > 0 of num / den (inf when none)."""
+        m = den > 0
+        return float(np.min(np.maximum(num[m], 0.0) / den[m])) if m.any() else np.inf
     for k, j in enumerate(js):
         # bound movement per unit capacity (a_i where the bound is a_i eta_j)
         dhi = np.where(qp.hi_idx == j, qp.hi_coef, 0.0)
@@ -162,6 +175,18 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
             held = ~free & ~coll
             signs = np.all(z[held & at_hi] >= -tol_z * bscale) and np.all(z[held & at_lo & ~at_hi] <= tol_z * bscale)
             oks.append(bool(inside and signs))
+        # distance to the nearest kink: free entries meeting a (moving)
+        # bound, held entries whose multiplier reaches zero
+        dists = []
+        for sgn in (1.0, -1.0):
+            f = free
+            d_hi = ratio((qp.hi - x0)[f & fin_hi], (sgn * (dx - dhi))[f & fin_hi])
+            d_lo = ratio((x0 - qp.lo)[f & fin_lo], (sgn * (dlo - dx))[f & fin_lo])
+            d_zh = ratio(z0[held_hi], (-sgn * dz)[held_hi])
+            d_zl = ratio(-z0[held_lo], (sgn * dz)[held_lo])
+            dists.append(min(d_hi, d_lo, d_zh, d_zl))
+        out["dist"][k] = min(dists)
+        out["curv"][k] = qp.r * float(dx @ dx)
         # h(x0 + s h dx) - h(x0) = s h g0'dx + (r/2) h^2 ||dx||^2  (exact for the quadratic)
         lin = float(g0 @ dx)
         quad = 0.5 * qp.r * h * h * float(dx @ dx)

@@ -337,6 +337,22 @@ def two_node(cA=20.0, cB=60.0, PA=300.0, PB=200.0, D=150.0, F=80.0, beta=10.0, T
     return Case(name="two_node", networks=[net], scenarios=[sc])
 
 
+def two_loads(PA=300.0, PB=200.0, F=80.0, DA=50.0, DB=150.0, cA=20.0, cB=60.0, beta=10.0):
+    """Two nodes with load at both: generator A (cost cA, capacity PA) and
+    load DA at node 0, generator B (cB, PB) and load DB at node 1, one line
+    0 -> 1 of capacity F; T = 1, no batteries.  Capacity boxes start at the
+    given values (which may be zero) and reach 400 MW above them."""
+    net = Network(
+        n_nodes=2, line_from=np.array([0], np.int32), line_to=np.array([1], np.int32),
+        line_beta=_f32([beta]), gen_node=np.array([0, 1], np.int32),
+        gen_kind=np.array([GAS, GAS], np.int32), gen_cost=_f32([cA, cB]),
+        gen_emis=_f32([GAS_EMIS, GAS_EMIS]), batt_node=np.zeros(0, np.int32),
+        eta_min=_f32([PA, PB, F]), eta_max=_f32([PA + 400, PB + 400, F + 400]),
+        gamma=_f32([1e5, 1e5, 1e5]))
+    sc = Scenario(network=0, T=1, avail=np.ones((2, 1)), load=_f32([[DA], [DB]]), weight=8760.0)
+    return Case(name="two_loads", networks=[net], scenarios=[sc])
+
+
 def single_node(costs, caps, D, kinds=None, T=1, avail=None):
     """One node, no lines, no batteries: the merit-order case."""
     G = len(costs)

@@ -2,20 +2,33 @@
 
 Calls only ``oracle/`` (and the seeded input generator).  For each listed
 configuration and scenario it solves the dispatch QP with the FP64 interior
-point + polish at capacities eta_min jittered by U[0, 1e-2] MW (seed 11),
-and stores the objective, the emissions and the per-scenario capacity
-gradient of h_s (not weighted) as JSON:
+point + polish at capacities eta_min jittered by U[0, 1e-2] MW (seed 11) and
+stores, as JSON:
+
+- the objective, the emissions and the planner objective h_s;
+- the per-scenario capacity gradient of h_s (not weighted by w_s), from the
+  least-squares adjoint (Section 2.2, implicit function theorem);
+- for every capacity, the central difference of h_s with h = 1e-3 MW from the
+  fixed-active-set re-solve (one factorisation, two back-solves per capacity)
+  and whether both ends verified as optimal ("fd_ok"); a coordinate that does
+  not verify has a kink of the piecewise-affine dispatch map within 1e-3 MW
+  and carries no derivative there;
+- the same verification over +-0.05 MW ("ok_wide");
+- per capacity, the distance to the nearest kink along it ("kink_distance",
+  MW, from a ratio test on the fixed-active-set step) and the curvature of
+  h_s along it ("curvature"): a solve whose duality gap is G determines the
+  derivative of a convex h_s only to within G / distance + curvature *
+  distance / 2;
+- a stratified 20-capacity subset among the verified coordinates: 8
+  generators (3 gas, 3 solar, 2 wind), the 8 lines with the largest gradient
+  magnitude (congested), 4 batteries.
 
     python tests/golden/make_golden.py 1 0 1      # config 1, scenarios 0 and 1
-    python tests/golden/make_golden.py 3 0        # config 3, scenario 0
-    python tests/golden/make_golden.py --spread 1 0   # add the kink spread to a stored file
-    python tests/golden/make_golden.py --spread-draw 3 1 0   # one draw of it (draws run in parallel)
+    python tests/golden/make_golden.py 3 1        # config 3, scenario 1
 
-The spread is the largest relative change of the oracle gradient when every
-capacity moves by U[-0.02, 0.02] MW (two draws): the GPU solves to a balance
-residual of about that size, so near a kink of the piecewise-affine dispatch
-map its gradient cannot be more accurate than this.  The moved gradients are
-stored too, so a test can take the same measure on any subset of capacities.
+The interior-point solution of each scenario is cached (uncompressed npz,
+not committed) under tests/golden/.cache/, so the derived values can be
+recomputed without the solve: a config-3 solve takes hours of CPU.
 """
 import json
 import os
@@ -24,7 +37,8 @@ import time
 
 import numpy as np
 
-ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from paper_2410_13055_amd import cases  # noqa: E402
@@ -32,82 +46,48 @@ from oracle import dispatch as D  # noqa: E402
 from oracle import gradient as Gm  # noqa: E402
 
 JITTER_SEED = 11
+FD_H = 1e-3
+WIDE_H = 0.05
 
 
 def golden_eta(case):
     return cases.jitter(case.eta_min(), JITTER_SEED, eta_min=case.eta_min(), eta_max=case.eta_max())
 
 
-SPREAD_MW = 0.02
+def _solution(case, cfg, s, qp):
+    """Polished oracle solution of scenario s, from the cache when present."""
+    cdir = os.path.join(HERE, ".cache")
+    path = os.path.join(cdir, f"config{cfg}_s{s}.npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        sol = D.Solution(x=z["x"], y=z["y"], z=z["z"], obj=float(z["obj"]), iters=int(z["iters"]),
+                         status=str(z["status"]), history=[], polished=bool(z["polished"]),
+                         degenerate=bool(z["degenerate"]), active_lo=z["active_lo"], active_hi=z["active_hi"])
+        return sol, True
+    sol = D.solve(qp)
+    os.makedirs(cdir, exist_ok=True)
+    np.savez(path, x=sol.x, y=sol.y, z=sol.z, obj=sol.obj, iters=sol.iters, status=sol.status,
+             polished=sol.polished, degenerate=sol.degenerate, active_lo=sol.active_lo, active_hi=sol.active_hi)
+    return sol, False
 
 
-def spread(cfg, s):
-    case = cases.by_id(cfg)
-    eta = golden_eta(case)
-    off = case.eta_offsets()
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_config{cfg}_s{s}.json")
-    with open(path) as fh:
-        out = json.load(fh)
-    g0 = np.array(out["grad"])
-    net = case.scenarios[s].network
-    worst = 0.0
-    moved = []
-    for k in range(2):
-        rng = np.random.Generator(np.random.PCG64(1000 + k))
-        ep = np.clip(eta + rng.uniform(-SPREAD_MW, SPREAD_MW, size=eta.shape), case.eta_min(), case.eta_max())
-        qp = D.assemble(case, s, ep[off[net]:off[net + 1]])
-        sol = D.solve(qp)
-        g = Gm.scenario_gradient(qp, sol, case.omega)["grad"]
-        moved.append([float(v) for v in g])
-        worst = max(worst, float(np.linalg.norm(g - g0) / np.linalg.norm(g0)))
-    out["grad_spread"] = worst
-    out["spread_grads"] = moved
-    out["spread_mw"] = SPREAD_MW
-    with open(path, "w") as fh:
-        json.dump(out, fh)
-    print(f"config {cfg} scenario {s}: gradient spread {worst:.2e}", flush=True)
-
-
-def spread_draw(cfg, s, k):
-    """One draw k of the spread, merged into the stored file under a lock
-    (several draws can run as separate processes).  The lock file is left in
-    place: removing it would let a process still waiting on the old file and
-    a newcomer on a fresh one both hold "the" lock."""
-    import fcntl
-    case = cases.by_id(cfg)
-    eta = golden_eta(case)
-    off = case.eta_offsets()
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_config{cfg}_s{s}.json")
-    net = case.scenarios[s].network
-    rng = np.random.Generator(np.random.PCG64(1000 + k))
-    ep = np.clip(eta + rng.uniform(-SPREAD_MW, SPREAD_MW, size=eta.shape), case.eta_min(), case.eta_max())
-    qp = D.assemble(case, s, ep[off[net]:off[net + 1]])
-    g = Gm.scenario_gradient(qp, D.solve(qp), case.omega)["grad"]
-    with open(path + ".lock", "w") as lk:
-        fcntl.flock(lk, fcntl.LOCK_EX)
-        with open(path) as fh:
-            out = json.load(fh)
-        g0 = np.array(out["grad"])
-        draws = dict(out.get("spread_draws", {}))
-        draws[str(k)] = [float(v) for v in g]
-        out["spread_draws"] = draws
-        out["spread_grads"] = [draws[d] for d in sorted(draws)]
-        out["grad_spread"] = max(float(np.linalg.norm(np.array(v) - g0) / np.linalg.norm(g0))
-                                 for v in out["spread_grads"])
-        out["spread_mw"] = SPREAD_MW
-        with open(path, "w") as fh:
-            json.dump(out, fh)
-    print(f"config {cfg} scenario {s} draw {k}: gradient spread so far {out['grad_spread']:.2e}", flush=True)
+def subset20(case, grad, ok):
+    """Stratified 20-capacity subset among the coordinates in ``ok``."""
+    net = case.networks[0]
+    G, L = net.n_gens, net.n_lines
+    rng = np.random.default_rng(20)
+    idx = []
+    for kind, n in ((cases.GAS, 3), (cases.SOLAR, 3), (cases.WIND, 2)):
+        cand = np.where((net.gen_kind == kind) & ok[:G])[0]
+        idx += [int(v) for v in rng.choice(cand, n, replace=False)]
+    lines = np.where(ok[G:G + L])[0]
+    idx += [int(G + v) for v in lines[np.argsort(-np.abs(grad[G + lines]))[:8]]]
+    bat = np.where(ok[G + L:])[0]
+    idx += [int(G + L + v) for v in rng.choice(bat, 4, replace=False)]
+    return idx
 
 
 def main():
-    if sys.argv[1] == "--spread-draw":
-        spread_draw(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]))
-        return
-    if sys.argv[1] == "--spread":
-        for s in sys.argv[3:] or ["0"]:
-            spread(int(sys.argv[2]), int(s))
-        return
     cfg = int(sys.argv[1])
     scen = [int(s) for s in sys.argv[2:]] or [0]
     case = cases.by_id(cfg)
@@ -117,21 +97,35 @@ def main():
         t0 = time.time()
         net = case.scenarios[s].network
         qp = D.assemble(case, s, eta[off[net]:off[net + 1]])
-        sol = D.solve(qp)
+        sol, cached = _solution(case, cfg, s, qp)
+        t_solve = time.time() - t0
         res = D.kkt_residual(qp, sol.x, sol.y)
         gr = Gm.scenario_gradient(qp, sol, case.omega)
+        fd = Gm.fixed_set_differences(qp, sol, case.omega, h=FD_H)
+        wide = Gm.fixed_set_differences(qp, sol, case.omega, h=WIDE_H)
+        ok = fd["ok"]
+        scale = np.abs(gr["grad"]).max()
+        agree = float(np.abs(fd["central"][ok] - gr["grad"][ok]).max(initial=0.0) / scale)
         out = {
             "config": cfg, "scenario": s, "omega": case.omega, "jitter_seed": JITTER_SEED,
             "cost": D.primal_objective(qp, sol.x), "emis": float(qp.emis @ sol.x),
             "h": D.planner_objective(qp, sol.x, case.omega), "kkt": res["kkt"],
-            "polished": bool(sol.polished), "kink": bool(gr["kink"]),
-            "grad": [float(v) for v in gr["grad"]], "seconds": time.time() - t0,
+            "polished": bool(sol.polished), "rank_deficient": bool(gr["rank_deficient"]),
+            "grad": [float(v) for v in gr["grad"]],
+            "fd_h": FD_H, "fd_central": [float(v) for v in fd["central"]],
+            "fd_ok": [int(v) for v in ok], "ok_wide": [int(v) for v in wide["ok"]], "wide_h": WIDE_H,
+            "kink_distance": [float(v) for v in fd["dist"]], "curvature": [float(v) for v in fd["curv"]],
+            "fd_vs_grad_max_rel": agree,
+            "subset20": subset20(case, gr["grad"], ok),
+            "solve_seconds": t_solve if not cached else None, "seconds": time.time() - t0,
         }
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_config{cfg}_s{s}.json")
+        path = os.path.join(HERE, f"oracle_config{cfg}_s{s}.json")
         with open(path, "w") as fh:
             json.dump(out, fh)
         print(f"config {cfg} scenario {s}: cost {out['cost']:.6e} kkt {res['kkt']:.1e} "
-              f"polished {sol.polished} kink {gr['kink']} {out['seconds']:.0f} s", flush=True)
+              f"polished {sol.polished} kinks within {FD_H} MW: {int((~ok).sum())} of {qp.K}, within "
+              f"{WIDE_H} MW: {int((~wide['ok']).sum())}; fd vs grad {agree:.1e}; {out['seconds']:.0f} s"
+              f"{' (cached solve)' if cached else ''}", flush=True)
 
 
 if __name__ == "__main__":

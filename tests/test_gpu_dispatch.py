@@ -239,8 +239,8 @@ def test_emissions_gradient_where_the_adjoint_is_nearly_zero():
     """100-node case at 200 $/t: most gas units sit at a bound, so the adjoint
     solution is small and its objective near zero; the adjoint solve must
     still stop (its gap is measured against the dual function at zero) and
-    match the oracle gradient (to the kink spread where the oracle flags a
-    kink)."""
+    match the oracle gradient over the coordinates at which the map is
+    differentiable (fixed-active-set verification at +-1e-3 MW)."""
     cs = cases.geo100()
     s, omega = 1, 200.0
     eta = _eta(cs, 5)
@@ -248,15 +248,30 @@ def test_emissions_gradient_where_the_adjoint_is_nearly_zero():
         p.solve(eta, [s])
         g, h, rc = p.grad([s], omega)
     assert rc == 0
-    _, sol, gr = _oracle(cs, s, eta, omega)
+    qp, sol, gr = _oracle(cs, s, eta, omega)
     w = cs.scenarios[s].weight
     ref = w * gr["grad"]
-    bar = 1e-3
-    if gr["kink"]:
-        rng = np.random.Generator(np.random.PCG64(1000))
-        ep = np.clip(eta + rng.uniform(-0.02, 0.02, size=eta.shape), cs.eta_min(), cs.eta_max())
-        _, _, g2 = _oracle(cs, s, ep, omega)
-        bar = max(bar, np.linalg.norm(w * g2["grad"] - ref) / np.linalg.norm(ref))
-    err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
-    print(f"\n[gpu] geo100 emissions gradient err {err:.2e} bar {bar:.2e}", flush=True)
-    assert err <= bar
+    ok = Gm.fixed_set_differences(qp, sol, omega, h=1e-3)["ok"]
+    err = np.linalg.norm((g - ref)[ok]) / np.linalg.norm(ref[ok])
+    print(f"\n[gpu] geo100 emissions gradient err {err:.2e} over {int(ok.sum())} of {ok.size} coordinates",
+          flush=True)
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("PA,PB,F,cA,cB", [(300.0, 200.0, 0.0, 20.0, 60.0), (300.0, 200.0, 0.0, 60.0, 20.0),
+                                          (300.0, 0.0, 80.0, 20.0, 60.0)])
+def test_zero_capacity_one_sided_gradient(PA, PB, F, cA, cB):
+    """A line or a generator at zero capacity: the GPU returns the derivative
+    for increasing capacity, -|z_f| for the line and -(pi_B - c_B) for the
+    generator, as the oracle does (whose value the closed forms pin)."""
+    cs = cases.two_loads(PA, PB, F, cA=cA, cB=cB)
+    eta = cs.eta_min()
+    with _plan(cs) as p:
+        cost, st, rc = p.solve(eta, [0])
+        assert rc == 0, st
+        g, _, _ = p.grad([0], 0.0, eta=eta)
+    qp, sol, gr = _oracle(cs, 0, eta)
+    ref = cs.scenarios[0].weight * gr["grad"]
+    print(f"\n[gpu] zero capacity: gpu {g} oracle {ref}", flush=True)
+    assert np.linalg.norm(g - ref) <= 1e-3 * np.linalg.norm(ref)
+    assert np.all(g <= 0.0)

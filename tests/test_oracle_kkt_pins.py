@@ -96,18 +96,8 @@ def test_box_violation():
 # zero capacity: the derivative for increasing capacity
 # --------------------------------------------------------------------------
 
-def _two_loads(PA, PB, F, DA=50.0, DB=150.0, cA=20.0, cB=60.0, beta=10.0):
-    """Two nodes with load at both: A (cheap unit, load DA) -> B (dear unit,
-    load DB), line capacity F."""
-    net = cases.Network(
-        n_nodes=2, line_from=np.array([0], np.int32), line_to=np.array([1], np.int32),
-        line_beta=cases._f32([beta]), gen_node=np.array([0, 1], np.int32),
-        gen_kind=np.array([cases.GAS, cases.GAS], np.int32), gen_cost=cases._f32([cA, cB]),
-        gen_emis=cases._f32([0.4, 0.4]), batt_node=np.zeros(0, np.int32),
-        eta_min=cases._f32([PA, PB, F]), eta_max=cases._f32([PA + 400, PB + 400, F + 400]),
-        gamma=cases._f32([1e5, 1e5, 1e5]))
-    sc = cases.Scenario(network=0, T=1, avail=np.ones((2, 1)), load=cases._f32([[DA], [DB]]), weight=8760.0)
-    return cases.Case(name="two_loads", networks=[net], scenarios=[sc])
+def _two_loads(PA, PB, F, **kw):
+    return cases.two_loads(PA, PB, F, **kw)
 
 
 def test_zero_line_capacity_one_sided_derivative():
@@ -276,3 +266,24 @@ def test_neighbour_and_capacity_columns_on_the_ring():
     np.testing.assert_allclose(X[:, 5 * T].sum(), eta[G + L:].sum(), rtol=1e-12)
     np.testing.assert_allclose(X[:, 5 * T + 1].sum(), 2 * eta[G:G + L].sum(), rtol=1e-12)
     np.testing.assert_allclose(X[:, 5 * T + 2].sum(), eta[:G][net.gen_cost > 0].sum(), rtol=1e-12)
+
+
+def test_kink_distance_on_the_two_node_closed_form():
+    """Two-node congested case (cA 20, cB 60, load 150 at B, line 80 MW):
+    raising the line capacity moves flow onto it one for one and takes B's
+    output down, which reaches zero at F = 150, 70 MW away; lowering it keeps
+    every classification until the box collapses at zero.  The nearest kink
+    along F is therefore 70 MW away, and the curvature of V along F is
+    r (|df|^2 + |dp_A|^2 + |dp_B|^2 + |dth|^2) = r (3 + 1 / (2 beta^2)).
+    The generators run below their capacities (A at 80 of 300 MW, B at 70 of
+    200 MW): lowering a capacity meets the output 220 and 130 MW away, and
+    along them V is flat."""
+    cs = cases.two_node(20.0, 60.0, 300.0, 200.0, 150.0, 80.0, 10.0)
+    qp, sol = D.solve_scenario(cs, 0, cs.eta_min())
+    fd = Gm.fixed_set_differences(qp, sol, 0.0, h=1e-3)
+    assert fd["dist"][2] == pytest.approx(70.0, rel=1e-9)
+    assert fd["dist"][0] == pytest.approx(220.0, rel=1e-9)
+    assert fd["dist"][1] == pytest.approx(130.0, rel=1e-9)
+    assert fd["curv"][0] == 0.0 and fd["curv"][1] == 0.0
+    beta = float(cs.networks[0].line_beta[0])
+    assert fd["curv"][2] == pytest.approx(cs.r * (3.0 + 1.0 / (2 * beta ** 2)), rel=1e-9)
