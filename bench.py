@@ -37,12 +37,13 @@ WORKLOADS = {
 
 
 def algorithmic_bytes(case, scen):
-    """Bytes one launch of each sweep must move (FP32 primal, FP64 dual):
+    """Bytes one launch of each sweep moves in this design (FP32 primal and
+    anchor, FP64 dual anchor, FP32 dual offset):
     variable sweep: read x and the anchor x0, write x (12 B per variable),
-    read every extrapolated dual once (8 B per row) and the availability
-    profile (4 B per generator-hour);
-    row sweep: read every variable once (4 B), read y and y0 and write y and
-    the extrapolated dual (32 B per row), read the load (4 B per node-hour)."""
+    gather every row's FP64 anchor and FP32 offset once (12 B per row) and
+    the availability profile (4 B per generator-hour);
+    row sweep: read every variable once (4 B), read and write the dual offset
+    (8 B per row), read the load (4 B per node-hour)."""
     nx = ny = gt = nt = 0
     for s in scen:
         sc = case.scenarios[s]
@@ -52,7 +53,7 @@ def algorithmic_bytes(case, scen):
         ny += (n.n_nodes + n.n_lines + n.n_batt) * T
         gt += n.n_gens * T
         nt += n.n_nodes * T
-    return dict(primal=12 * nx + 8 * ny + 4 * gt, dual=4 * nx + 32 * ny + 4 * nt, n_x=nx, n_y=ny)
+    return dict(primal=12 * nx + 12 * ny + 4 * gt, dual=4 * nx + 8 * ny + 4 * nt, n_x=nx, n_y=ny)
 
 
 def sec8d_bytes(case, scen):
@@ -225,10 +226,10 @@ def summarize(stats_csv, pmc_runs, workload_id, commands):
 
 
 PROFILE_COMMANDS = [
-    "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_c1 -o run -- "
-    "python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu --no-hbm-case",
+    "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/prof_c4 -o run -- "
+    "python3 <repo>/bench.py --steps 2 --warmup 0 --no-cpu --no-arms",
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch_<B> -o run -- "
-    "python3 <repo>/bench.py --pmc-run --pmc-block <B>      (B = 128, 256, 512)",
+    "python3 <repo>/bench.py --pmc-run --pmc-block <B>      (B = 256, the tuned block)",
     "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write_<B> -o run -- "
     "python3 <repo>/bench.py --pmc-run --pmc-block <B>",
     "python bench.py --summarize <out>",
@@ -236,32 +237,43 @@ PROFILE_COMMANDS = [
 
 
 def write_profiles(d):
+    """profiles/sweeps_geo1000.md and profiles/traffic.md from the rocprofv3
+    outputs of PROFILE_COMMANDS under <d>."""
+    import csv
+    import glob
     runs = []
-    for blk in (128, 256, 512):
-        with open(os.path.join(d, f"pmc_{blk}.out")) as fh:
+    for out in sorted(glob.glob(os.path.join(d, "pmc_[0-9]*.out"))):
+        if not os.path.basename(out)[4:-4].isdigit():
+            continue
+        blk = int(os.path.basename(out)[4:-4])
+        with open(out) as fh:
             line = next(l for l in fh if l.startswith('{"pmc_run"'))
         runs.append((os.path.join(d, f"pmc_fetch_{blk}", "run_counter_collection.csv"),
                      os.path.join(d, f"pmc_write_{blk}", "run_counter_collection.csv"), line))
-    summary, table = summarize(os.path.join(d, "prof_c1", "run_kernel_stats.csv"), runs, 1, PROFILE_COMMANDS)
-    # the bench line of the traced run, beside the profiler's average for the
-    # same (timed) instantiation of the roofline kernel
-    import csv
-    with open(os.path.join(d, "prof_c1.out")) as fh:
+    summary, table = summarize(os.path.join(d, "prof_c4", "run_kernel_stats.csv"), runs, 4, PROFILE_COMMANDS)
+    # the bench line of the traced run, beside the profiler's averages for the
+    # same (timed) instantiations of the two sweep kernels
+    with open(os.path.join(d, "prof_c4.out")) as fh:
         line = json.loads(next(l for l in fh if l.startswith('{"metric"')))
     roof = line["roofline"]
-    name = f"void gp::{roof['kernel']}<{roof['launch']['block']}, 1>"
-    with open(os.path.join(d, "prof_c1", "run_kernel_stats.csv")) as fh:
-        prof_us = next(float(r["AverageNs"]) / 1e3 for r in csv.DictReader(fh) if r["Name"].startswith(name))
-    summary += ("\n## Roofline kernel: bench.py against the profiler (same run)\n\n"
-                f"bench.py (HIP events, {roof['kernel']}, block {roof['launch']['block']}): "
-                f"{roof['ms_per_launch'] * 1e3:.2f} us per launch, {roof['achieved']} GB/s of algorithmic bytes "
-                f"({roof['bytes_per_launch']} B), {roof['frac'] * 100:.1f} % of 8 TB/s; rocprofv3 average of "
-                f"`{name[len('void gp::'):]}`: {prof_us:.2f} us.  Headline value of that run: "
-                f"{line['value']} {line['unit']}.\n")
-    with open(os.path.join(ROOT, "profiles", "sweeps_geo240.md"), "w") as fh:
+    blk = roof["launch"]["block"]
+    prof = {}
+    with open(os.path.join(d, "prof_c4", "run_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            for k in ("k_dual", "k_primal"):
+                if r["Name"].startswith(f"void gp::{k}<{blk}, 1>"):
+                    prof[k] = float(r["AverageNs"]) / 1e3
+    summary += ("\n## Roofline: bench.py against the profiler (same run)\n\n"
+                f"bench.py (HIP events, block {blk}, 16 scenarios): k_dual {roof['ms_dual'] * 1e3:.2f} us + "
+                f"k_primal {roof['ms_primal'] * 1e3:.2f} us = {roof['ms_per_iteration'] * 1e3:.2f} us per ADMM "
+                f"iteration; {roof['bytes_per_iteration']} algorithmic bytes per iteration -> {roof['achieved']} GB/s, "
+                f"{roof['frac'] * 100:.1f} % of 8 TB/s.  rocprofv3 averages of the same instantiations: k_dual "
+                f"{prof.get('k_dual', float('nan')):.2f} us, k_primal {prof.get('k_primal', float('nan')):.2f} us.  "
+                f"Headline value of that (2-step) run: {line['value']} {line['unit']}.\n")
+    with open(os.path.join(ROOT, "profiles", "sweeps_geo1000.md"), "w") as fh:
         fh.write(summary)
     with open(os.path.join(ROOT, "profiles", "traffic.md"), "w") as fh:
-        fh.write(table)
+        fh.write(table.replace("sweeps_geo240.md", "sweeps_geo1000.md"))
 
 
 def write_mlp_profile(d):
@@ -782,7 +794,7 @@ def headline_leg(args):
     # training data (previous-iterate planning runs at other storage costs),
     # then the two warm arms; each piece runs only while the budget allows it
     need_collect = len(args.ws_train_prices) * M * per_step * 1.1
-    if left() > need_collect + 2 * M * per_step + 60:
+    if args.arms and left() > need_collect + 2 * M * per_step + 60:
         ws = LearnedWarmStart(plan, T, seed=0)
         t1 = time.perf_counter()
         for i, price in enumerate(args.ws_train_prices):
@@ -885,6 +897,8 @@ def main():
     ap.add_argument("--batch", type=int, default=4, help="scenarios per planning step (headline)")
     ap.add_argument("--pool", type=int, default=16, help="scenarios the batches are drawn from (headline)")
     ap.add_argument("--arm-steps", type=int, default=6, help="steps of the warm-start arms (headline)")
+    ap.add_argument("--no-arms", dest="arms", action="store_false",
+                    help="headline: skip the warm-start arms and their training (profiled runs)")
     ap.add_argument("--budget", type=float, default=500.0,
                     help="seconds after which the headline run skips its untimed extras")
     ap.add_argument("--sweep-iters", type=int, default=50)
@@ -917,7 +931,7 @@ def main():
                          "under DIR (prof_c1/, pmc_fetch_<block>/, pmc_write_<block>/, pmc_<block>.out)")
     args = ap.parse_args()
     if args.summarize:
-        if os.path.exists(os.path.join(args.summarize, "prof_c1")):
+        if os.path.exists(os.path.join(args.summarize, "prof_c4")):
             write_profiles(args.summarize)
         if os.path.exists(os.path.join(args.summarize, "prof_mlp")):
             write_mlp_profile(args.summarize)
@@ -951,11 +965,13 @@ def main():
     if args.plan_warm:
         plan_warm_leg(args)
         return
-    if args.config == 4:
+    if args.config == 4 and not args.pmc_run:
         headline_leg(args)
         return
     case = cases.by_id(args.config)
-    scen = list(range(len(case.scenarios)))
+    # the counter run on the headline workload measures the roofline's batch:
+    # 16 of its scenarios
+    scen = list(range(16 if args.config == 4 else len(case.scenarios)))
     sh = case.scenario_hours(scen)
     eta = case.eta_min()
     omega = case.omega
@@ -975,8 +991,9 @@ def main():
         torch.cuda.synchronize()
         assert float(total) == float(1 << 28)
         ab = algorithmic_bytes(case, scen)
-        print(json.dumps({"pmc_run": WORKLOADS[args.config], "ms_dual": md, "ms_primal": mp,
-                          "block": tb, "variant": tv, "copy_bytes": 1 << 30, **ab}), flush=True)
+        print(json.dumps({"pmc_run": WORKLOADS[args.config] + f" (sweeps over {len(scen)} scenarios)",
+                          "ms_dual": md, "ms_primal": mp, "block": tb, "variant": tv, "copy_bytes": 1 << 30,
+                          "sec8d_bytes_per_iteration": sec8d_bytes(case, scen), **ab}), flush=True)
         plan.close()
         return
     plan = gridplan.Plan(case, gridplan.options(), stream=gridplan.current_stream())

@@ -120,11 +120,17 @@ struct Args {
   const float* eta;         // capacities (FP32)
   // state
   float* x;       // primal state, FP32
-  float* x0;
+  float* x0;      // its anchor
   float* xhat;
-  double* y;      // duals, FP64: prices reach the unserved-load penalty while
-  double* y0;     // the primal update needs E'y - q to far better than FP32
-  double* ybar;   // resolution there
+  // Duals.  The anchor y0 and the output yhat are FP64: prices reach the
+  // unserved-load penalty while the primal update needs E'y - q to far
+  // better than FP32 resolution there.  The iterate is held as an FP32
+  // offset from the anchor: dbar = ybar - y0, the extrapolated dual
+  // 2 yhat - y of the last row sweep; the next Halpern iterate is
+  // y0 + lambda * dbar.  Offsets stay small between restarts (the anchor
+  // moves to the output point at each), so FP32 resolves them.
+  double* y0;
+  float* dbar;
   double* yhat;
   const uint8_t* amask;     // adjoint mode: 1 = entry held at its bound
   // per-scenario control

@@ -11,7 +11,13 @@
 //                                          circulant inverse per battery chain
 //   x^ = clip((c rho x + E'(2y^ - y) - q) / (r + c rho), lo, hi)
 // wrapped in a reflected Halpern iteration with an anchor (x0, y0) that the
-// host moves at adaptive restarts.  c is a per-scenario primal weight.
+// host moves at adaptive restarts.  c is a per-scenario primal weight.  The
+// dual iterate is carried as one FP32 offset from its FP64 anchor (the
+// extrapolated dual of the last row sweep, dbar = 2 y^ - y - y0); with
+// lambda_k = (k + 1) / (k + 2) the Halpern step for the duals reads
+//   y_k - y0 = lambda_{k-1} dbar_{k-1},   dbar_k = (y_k - y0) - 2 c S (E x - e),
+// so a row sweep reads and writes 4 bytes per row and the variable sweep
+// gathers y0 + dbar.
 //
 // All sweeps are memory-bound: no dense contraction appears, so nothing uses
 // MFMA.  Every array is [device][hour] per scenario, so consecutive lanes
@@ -87,14 +93,13 @@ __device__ __forceinline__ float soc_residual(const NetDev& nt, const float* xs,
   return psoc[t] - psoc[tp] - eff * pch[t] + pdis[t];
 }
 
-__device__ __forceinline__ void dual_update(const Args& a, int64_t row, double step, double lam,
+// lamp = lambda_{k-1} = k / (k + 1) (0 right after a restart, where the
+// stored offset is zero anyway)
+__device__ __forceinline__ void dual_update(const Args& a, int64_t row, double step, double lamp,
                                             int check) {
-  const double yv = a.y[row];
-  const double yh = yv - step;
-  const double e2 = 2.0 * yh - yv;
-  a.ybar[row] = e2;
-  a.y[row] = lam * e2 + (1.0 - lam) * a.y0[row];
-  if (check) a.yhat[row] = yh;
+  const double d = lamp * (double)a.dbar[row];  // y_k - y0
+  a.dbar[row] = (float)(d - 2.0 * step);
+  if (check) a.yhat[row] = a.y0[row] + (d - step);
 }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -116,21 +121,34 @@ __device__ __forceinline__ void std4(double* p, const double (&v)[4]) {
 }
 
 // dual_update on rows [row, row + 4)
-__device__ __forceinline__ void dual_update4(const Args& a, int64_t row, const double (&step)[4], double lam,
+__device__ __forceinline__ void dual_update4(const Args& a, int64_t row, const double (&step)[4], double lamp,
                                              int check) {
-  double yv[4], y0[4], yh[4], e2[4], yn[4];
-  ldd4(a.y + row, yv);
-  ldd4(a.y0 + row, y0);
+  const f4 db = ld4(a.dbar + row);
+  double d[4];
+  f4 nb;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    yh[q] = yv[q] - step[q];
-    e2[q] = 2.0 * yh[q] - yv[q];
-    yn[q] = lam * e2[q] + (1.0 - lam) * y0[q];
+    d[q] = lamp * (double)db[q];
+    nb[q] = (float)(d[q] - 2.0 * step[q]);
   }
-  std4(a.ybar + row, e2);
-  std4(a.y + row, yn);
-  if (check) std4(a.yhat + row, yh);
+  st4(a.dbar + row, nb);
+  if (check) {
+    double y0[4], yh[4];
+    ldd4(a.y0 + row, y0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yh[q] = y0[q] + (d[q] - step[q]);
+    std4(a.yhat + row, yh);
+  }
 }
+
+// the extrapolated dual y0 + dbar of rows [off, off + 4) (FP64)
+__device__ __forceinline__ void ldy4(const Args& a, int64_t off, double (&v)[4]) {
+  ldd4(a.y0 + off, v);
+  const f4 db = ld4(a.dbar + off);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] += (double)db[q];
+}
+__device__ __forceinline__ double ldy(const Args& a, int64_t off) { return a.y0[off] + (double)a.dbar[off]; }
 
 // Balance and flow rows, four hours per thread (T divisible by 4, so the
 // four rows share their node or line).
@@ -209,13 +227,12 @@ __device__ __forceinline__ void soc_chains4(const Args& a, const Tile& tl, const
   const int ch = (int)threadIdx.x / T4, t0 = 4 * ((int)threadIdx.x - ch * T4);
   const bool on = ch < tl.count;
   float* e = sres + 2 * ch * T;
-  double yv[4], y0[4];
+  f4 db = {0.f, 0.f, 0.f, 0.f};
   int64_t row = 0;
   if (on) {
     const int kb = tl.start + ch;
     row = sc.yoff + (int64_t)(nt.N + nt.L) * TT + (int64_t)kb * TT + t0;
-    ldd4(a.y + row, yv);
-    ldd4(a.y0 + row, y0);
+    db = ld4(a.dbar + row);
     const float* pch = a.x + sc.xoff + (int64_t)(nt.G + nt.L + nt.N) * TT + (int64_t)kb * TT;
     const float* pdis = pch + (int64_t)nt.B * TT;
     const float* psoc = pdis + (int64_t)nt.B * TT;
@@ -254,16 +271,24 @@ __device__ __forceinline__ void soc_chains4(const Args& a, const Tile& tl, const
       for (int u = 0; u < 4; ++u) acc[u] += hv * (m[u + jj] + m[u - jj]);
     }
   }
-  double yh[4], e2[4], yn[4];
+  double step[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) step[u] = c * (double)acc[u];
+  f4 nb;
+  double d[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    yh[u] = yv[u] - c * (double)acc[u];
-    e2[u] = 2.0 * yh[u] - yv[u];
-    yn[u] = lam * e2[u] + (1.0 - lam) * y0[u];
+    d[u] = lam * (double)db[u];
+    nb[u] = (float)(d[u] - 2.0 * step[u]);
   }
-  std4(a.ybar + row, e2);
-  std4(a.y + row, yn);
-  if (check) std4(a.yhat + row, yh);
+  st4(a.dbar + row, nb);
+  if (check) {
+    double y0[4], yh[4];
+    ldd4(a.y0 + row, y0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yh[u] = y0[u] + (d[u] - step[u]);
+    std4(a.yhat + row, yh);
+  }
 }
 
 // One row tile of the dual sweep.  sres: LDS of at least T floats.  Every
@@ -279,7 +304,7 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
   const int64_t TT = T;
   const double c = a.cw[s];
   const int k = a.kbase[s] + j;
-  const double lam = (double)(k + 1) / (double)(k + 2);
+  const double lam = (double)k / (double)(k + 1);  // lambda of the previous iteration
   const float* xs = a.x + sc.xoff;
   if (tl.cls == (RC_SOC | kTileVec4)) {
     soc_chains4(a, tl, sc, nt, c, lam, check, sres);
@@ -374,16 +399,16 @@ struct Upd {
   }
 };
 
-// E'y for the angle of node n at hour t: sum over incident lines of
-// (+beta if the node is the line's 'to' end, -beta if 'from') * mu
-__device__ __forceinline__ double angle_ety(const Args& a, const NetDev& nt, const double* yf, int T,
-                                            int n, int t) {
+// E'ybar for the angle of node n at hour t: sum over incident lines of
+// (+beta if the node is the line's 'to' end, -beta if 'from') * mu, with the
+// flow duals mu = y0 + dbar from offset yf of the flow rows
+__device__ __forceinline__ double angle_ety(const Args& a, const NetDev& nt, int64_t yf, int T, int n, int t) {
   const int e0 = a.ang_ptr[nt.aptr_off + n], e1 = a.ang_ptr[nt.aptr_off + n + 1];
   double ey = 0.0;
   for (int e = e0; e < e1; ++e) {
     const int code = a.ang[e];
     const int l = code >> 1;
-    const double bv = (double)a.line_beta[nt.line_off + l] * yf[(int64_t)l * T + t];
+    const double bv = (double)a.line_beta[nt.line_off + l] * ldy(a, yf + (int64_t)l * T + t);
     ey += (code & 1) ? -bv : bv;
   }
   return ey;
@@ -423,9 +448,9 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
   const int s = tl.scen;
   const int T = sc.T;
   const int64_t TT = T;
-  const double* yb = a.ybar + sc.yoff;
-  const double* yf = yb + (int64_t)nt.N * TT;
-  const double* ys = yf + (int64_t)nt.L * TT;
+  const int64_t yb = sc.yoff;                 // balance rows
+  const int64_t yf = yb + (int64_t)nt.N * TT;  // flow rows
+  const int64_t ys = yf + (int64_t)nt.L * TT;  // SOC rows
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
   const f4 inf = {GP_INF, GP_INF, GP_INF, GP_INF};
   double ey[4];
@@ -435,7 +460,7 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
       const int n = a.gen_node[nt.gen_off + g];
       const f4 hi = ld4(a.avail + sc.aoff + i) * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
-      ldd4(yb + (int64_t)n * TT + t, ey);
+      ldy4(a, yb + (int64_t)n * TT + t, ey);
       upd4(u, i, ey, q, a.w.wb, zero, hi);
       break;
     }
@@ -443,9 +468,9 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
       const int l = i / T, t = i - l * T;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
       double pto[4], pfr[4], mu[4];
-      ldd4(yb + (int64_t)to * TT + t, pto);
-      ldd4(yb + (int64_t)fr * TT + t, pfr);
-      ldd4(yf + i, mu);
+      ldy4(a, yb + (int64_t)to * TT + t, pto);
+      ldy4(a, yb + (int64_t)fr * TT + t, pfr);
+      ldy4(a, yf + i, mu);
 #pragma unroll
       for (int k = 0; k < 4; ++k) ey[k] = pto[k] - pfr[k] + mu[k];
       const float cap = a.eta[nt.eta_off + nt.G + l];
@@ -463,12 +488,12 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
         const int l = code >> 1;
         const double bv = (code & 1) ? -(double)a.line_beta[nt.line_off + l] : (double)a.line_beta[nt.line_off + l];
         double mu[4];
-        ldd4(yf + (int64_t)l * TT + t, mu);
+        ldy4(a, yf + (int64_t)l * TT + t, mu);
 #pragma unroll
         for (int k = 0; k < 4; ++k) ey[k] += bv * mu[k];
       }
       upd4(u, (int64_t)(nt.G + nt.L) * TT + i, ey, 0.f, a.cwf[s] * a.rho_th[nt.node_off + n], -inf, inf);
-      ldd4(yb + i, ey);
+      ldy4(a, yb + i, ey);
       upd4(u, (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i, ey, a.mode ? 0.f : a.lambda_u, a.w.wu, zero,
            inf);
       break;
@@ -477,9 +502,9 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
       const int kb = i / T, t = i - kb * T;
       const int n = a.batt_node[nt.batt_off + kb];
       double pb[4], nu[4], e[4];
-      ldd4(yb + (int64_t)n * TT + t, pb);
-      ldd4(ys + i, nu);
-      const double nu_next = ys[(int64_t)kb * TT + ((t + 4 == T) ? 0 : t + 4)];
+      ldy4(a, yb + (int64_t)n * TT + t, pb);
+      ldy4(a, ys + i, nu);
+      const double nu_next = ldy(a, ys + (int64_t)kb * TT + ((t + 4 == T) ? 0 : t + 4));
       const float cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
       const f4 hic = {cap, cap, cap, cap};
       const f4 his = hic * a.hours;
@@ -523,22 +548,22 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
   const int k = a.kbase[s] + j;
   Upd u{a.x + sc.xoff, a.x0 + sc.xoff, a.xhat + sc.xoff, a.amask ? a.amask + sc.xoff : nullptr,
         a.cw[s], (float)(k + 1) / (float)(k + 2), a.r, check, a.mode};
-  const double* yb = a.ybar + sc.yoff;
-  const double* yf = yb + (int64_t)nt.N * TT;
-  const double* ys = yf + (int64_t)nt.L * TT;
+  const int64_t yb = sc.yoff;                 // balance rows
+  const int64_t yf = yb + (int64_t)nt.N * TT;  // flow rows
+  const int64_t ys = yf + (int64_t)nt.L * TT;  // SOC rows
   switch (tl.cls) {
     case VC_GEN: {
       const int g = i / T, t = i - g * T;
       const int n = a.gen_node[nt.gen_off + g];
       const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
-      u(i, yb[(int64_t)n * TT + t], q, a.w.wb, 0.f, hi);
+      u(i, ldy(a, yb + (int64_t)n * TT + t), q, a.w.wb, 0.f, hi);
       break;
     }
     case VC_LINE: {
       const int l = i / T, t = i - l * T;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-      const double ey = yb[(int64_t)to * TT + t] - yb[(int64_t)fr * TT + t] + yf[i];
+      const double ey = ldy(a, yb + (int64_t)to * TT + t) - ldy(a, yb + (int64_t)fr * TT + t) + ldy(a, yf + i);
       const float cap = a.eta[nt.eta_off + nt.G + l];
       u((int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + a.cwf[s] * a.w.wf, -cap, cap);
       break;
@@ -547,16 +572,16 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
       const int n = i / T, t = i - n * T;
       const double ey = angle_ety(a, nt, yf, T, n, t);
       u((int64_t)(nt.G + nt.L) * TT + i, ey, 0.f, a.cwf[s] * a.rho_th[nt.node_off + n], -GP_INF, GP_INF);
-      u((int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i, yb[i], a.mode ? 0.f : a.lambda_u,
+      u((int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i, ldy(a, yb + i), a.mode ? 0.f : a.lambda_u,
         a.w.wu, 0.f, GP_INF);
       break;
     }
     default: {  // VC_BATT
       const int kb = i / T, t = i - kb * T;
       const int n = a.batt_node[nt.batt_off + kb];
-      const double pb = yb[(int64_t)n * TT + t];
-      const double nu = ys[i];
-      const double nu1 = ys[(int64_t)kb * TT + ((t + 1 == T) ? 0 : t + 1)];
+      const double pb = ldy(a, yb + (int64_t)n * TT + t);
+      const double nu = ldy(a, ys + i);
+      const double nu1 = ldy(a, ys + (int64_t)kb * TT + ((t + 1 == T) ? 0 : t + 1));
       const float cap = a.eta[nt.eta_off + nt.G + nt.L + kb];
       const int64_t base = (int64_t)(nt.G + nt.L + nt.N) * TT;
       const int64_t BT = (int64_t)nt.B * TT;
@@ -894,7 +919,7 @@ __global__ __launch_bounds__(BS) void k_reduce(Args a) {
 // ----------------------------------------------------------------------------
 
 // Start / restart of the scenarios with restart[s] set.  The output point is
-// (xhat, yhat); (x0, y0) the anchors; ybar the extrapolated dual.
+// (xhat, yhat); (x0, y0) the anchors; dbar the dual offset from y0.
 //   RESET_WARM    everything from the output point (restart, warm start)
 //   RESET_COLD    everything zero
 //   RESET_PROBE   output point zero, iterate and anchors kept (a check pass
@@ -967,9 +992,8 @@ __global__ __launch_bounds__(BS) void k_reset(Args a, int mode) {
       continue;
     }
     const double v = mode == RESET_COLD ? 0.0 : mode == RESET_RESTORE ? a.y0[g] : a.yhat[g];
-    a.y[g] = v;
     a.y0[g] = v;
-    a.ybar[g] = v;
+    a.dbar[g] = 0.f;
     a.yhat[g] = v;
   }
 }

@@ -172,11 +172,13 @@ struct gp_plan {
   DevBuf<float> d_gen_cost, d_gen_emis, d_line_beta, d_sig_bal, d_rho_th, d_taps, d_avail, d_load,
       d_eta;
   DevBuf<float> d_x, d_x0, d_xhat;
-  DevBuf<double> d_y, d_y0, d_ybar, d_yhat;
+  DevBuf<double> d_y0, d_yhat;
+  DevBuf<float> d_dbar;
   DevBuf<uint8_t> d_mask;
   // adjoint state (allocated on first use)
   DevBuf<float> a_x, a_x0, a_xhat;
-  DevBuf<double> a_y, a_y0, a_ybar, a_yhat;
+  DevBuf<double> a_y0, a_yhat;
+  DevBuf<float> a_dbar;
   // per-scenario control
   DevBuf<float> d_cw, d_cwf;
   DevBuf<int32_t> d_kbase, d_active, d_restart;
@@ -503,9 +505,8 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->d_x0.alloc(xoff);
   p->d_xhat.alloc(xoff);
   p->d_mask.alloc(xoff);
-  p->d_y.alloc(yoff);
   p->d_y0.alloc(yoff);
-  p->d_ybar.alloc(yoff);
+  p->d_dbar.alloc(yoff);
   p->d_yhat.alloc(yoff);
   p->d_cw.alloc(p->S);
   p->d_cwf.alloc(p->S);
@@ -521,9 +522,8 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   HIPCHK(hipMemsetAsync(p->d_x.p, 0, xoff * sizeof(float), st));
   HIPCHK(hipMemsetAsync(p->d_x0.p, 0, xoff * sizeof(float), st));
   HIPCHK(hipMemsetAsync(p->d_xhat.p, 0, xoff * sizeof(float), st));
-  HIPCHK(hipMemsetAsync(p->d_y.p, 0, yoff * sizeof(double), st));
   HIPCHK(hipMemsetAsync(p->d_y0.p, 0, yoff * sizeof(double), st));
-  HIPCHK(hipMemsetAsync(p->d_ybar.p, 0, yoff * sizeof(double), st));
+  HIPCHK(hipMemsetAsync(p->d_dbar.p, 0, yoff * sizeof(float), st));
   HIPCHK(hipMemsetAsync(p->d_yhat.p, 0, yoff * sizeof(double), st));
   p->d_qc.alloc(2 * kQueueWords);
   p->d_qd.alloc(2);
@@ -580,18 +580,16 @@ Args make_args(gp_plan* p, int adjoint) {
     a.x = p->d_x.p;
     a.x0 = p->d_x0.p;
     a.xhat = p->d_xhat.p;
-    a.y = p->d_y.p;
     a.y0 = p->d_y0.p;
-    a.ybar = p->d_ybar.p;
+    a.dbar = p->d_dbar.p;
     a.yhat = p->d_yhat.p;
     a.amask = nullptr;
   } else {
     a.x = p->a_x.p;
     a.x0 = p->a_x0.p;
     a.xhat = p->a_xhat.p;
-    a.y = p->a_y.p;
     a.y0 = p->a_y0.p;
-    a.ybar = p->a_ybar.p;
+    a.dbar = p->a_dbar.p;
     a.yhat = p->a_yhat.p;
     a.amask = p->d_mask.p;
   }
@@ -1260,9 +1258,8 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
       p->a_x.alloc(p->nx_tot);
       p->a_x0.alloc(p->nx_tot);
       p->a_xhat.alloc(p->nx_tot);
-      p->a_y.alloc(p->ny_tot);
       p->a_y0.alloc(p->ny_tot);
-      p->a_ybar.alloc(p->ny_tot);
+      p->a_dbar.alloc(p->ny_tot);
       p->a_yhat.alloc(p->ny_tot);
     }
     drop_graph(p);
