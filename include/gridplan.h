@@ -275,6 +275,22 @@ int mlp_set_params(gp_mlp* m, const float* w_in);  /* host [n] */
 /* Y [rows x n_out] = net(X [rows x n_in]); on_device selects device (1) or
  * host (0) pointers for X and Y. */
 int mlp_forward(gp_mlp* m, const float* X, int64_t rows, int32_t on_device, float* Y);
+/* mlp_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, with the layer activations in a file-scope device
+ * array of 64 MiB (one per GPU, held until the process ends; its device
+ * address is taken once per device by mlp_init) instead of buffers the
+ * library allocates.  Allocates nothing and does not synchronise: the work
+ * is enqueued on the network's stream and Y_dev is ready when the stream
+ * reaches it.  X_dev [rows x n_in] and Y_dev [rows x n_out] are row-major
+ * FP32 DEVICE buffers owned by the caller.  rows may not exceed what the
+ * array holds for this network (2 * rows * max(n_in rounded up to 8, width)
+ * BF16 entries): *max_rows (nullable) receives that limit, and larger rows
+ * fail with GP_EINVAL (split the call).  Every call on a GPU uses that GPU's
+ * one array: calls that overlap on one GPU (several streams, or several
+ * networks) race and must be ordered by the caller.  Nothing in the array
+ * needs to start at zero (each call writes what it reads). */
+int mlp_forward_noalloc(gp_mlp* m, const float* X_dev, int64_t rows, float* Y_dev, int64_t* max_rows);
 /* Mean squared error over all outputs and its parameter gradient (host
  * [n], nullable). */
 int mlp_loss_grad(gp_mlp* m, const float* X, const float* T, int64_t rows, int32_t on_device, double* loss,

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -445,6 +446,32 @@ void launch_gemm(bool ta, bool tb, const __bf16* A, int lda, int Ka, const __bf1
 
 int nblk(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
+// Scratch of the allocation-free forward pass (mlp_forward_noalloc): two BF16
+// activation buffers that the layers alternate between.  One copy per GPU,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; kernels get the device address taken once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of the current device's scratch (taken on first use)
+void* scratch_address() {
+  int dev = 0;
+  MCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) mfail(GP_EINVAL, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      mfail(GP_EHIP, "hipGetSymbolAddress of the forward scratch failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 struct gp_mlp {
@@ -651,6 +678,7 @@ int mlp_init(gp_mlp** out, int32_t n_in, int32_t width, int32_t hidden_layers, i
       MCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
       m->own_stream = true;
     }
+    (void)scratch_address();  // the allocation-free forward's buffer on this device
     m->dims.push_back(n_in);
     for (int l = 0; l < hidden_layers; ++l) m->dims.push_back(width);
     m->dims.push_back(n_out);
@@ -752,6 +780,49 @@ int mlp_forward(gp_mlp* m, const float* X, int64_t rows, int32_t on_device, floa
     MCHK(hipMemcpyAsync(Y, src, n * sizeof(float), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                         m->stream));
     MCHK(hipStreamSynchronize(m->stream));
+    return GP_OK;
+  });
+}
+
+int mlp_forward_noalloc(gp_mlp* m, const float* X_dev, int64_t rows, float* Y_dev, int64_t* max_rows) {
+  if (!m) return GP_EINVAL;
+  return mguard(m, [&] {
+    // two BF16 buffers of rows x (widest layer input) elements
+    int wmax = m->n_pad;
+    for (int l = 1; l < m->L; ++l) wmax = std::max(wmax, m->dims[l]);
+    const int64_t per_row = 2 * (int64_t)wmax * (int64_t)sizeof(__bf16);
+    const int64_t cap = (int64_t)(kScratchBytes / (size_t)per_row);
+    if (max_rows) *max_rows = cap;
+    if (!X_dev || !Y_dev) mfail(GP_EINVAL, "X and Y must not be NULL");
+    check_dims(m, rows);
+    if (rows > cap)
+      mfail(GP_EINVAL, "%lld rows exceed the %lld that the %zu-byte forward scratch holds for this network",
+            (long long)rows, (long long)cap, kScratchBytes);
+    unsigned char* base = (unsigned char*)scratch_address();
+    __bf16* buf[2] = {(__bf16*)base, (__bf16*)(base + (size_t)rows * wmax * sizeof(__bf16))};
+    hipStream_t st = m->stream;
+    // input cast (and standardisation) into the zero-padded layout; every
+    // entry of [rows x n_pad] is written, so nothing needs clearing
+    hipLaunchKernelGGL(k_cast_input, dim3(nblk(rows * m->n_pad)), dim3(256), 0, st, X_dev, buf[0], rows,
+                       m->dims[0], m->n_pad, m->scaled ? m->xmu.p : nullptr, m->scaled ? m->xisd.p : nullptr);
+    MCHK(hipGetLastError());
+    for (int l = 0; l < m->L; ++l) {
+      const int N = m->dims[l + 1];
+      const int K = l == 0 ? m->n_pad : m->dims[l];
+      const __bf16* Wt = m->wbt.p + m->wtoff[l];
+      const float* b = m->w.p + m->boff[l];
+      if (l + 1 < m->L)
+        launch_gemm(false, true, buf[l & 1], K, K, Wt, K, K, nullptr, buf[(l + 1) & 1], b, (int)rows, N, K,
+                    EPI_BIAS_RELU, 0, st);
+      else
+        launch_gemm(false, true, buf[l & 1], K, K, Wt, K, K, Y_dev, nullptr, b, (int)rows, N, K, EPI_BIAS, 0, st);
+    }
+    if (m->scaled) {  // back to target units, in place
+      const int64_t n = rows * m->dims.back();
+      hipLaunchKernelGGL(k_unscale, dim3(nblk(n)), dim3(256), 0, st, Y_dev, Y_dev, n, m->dims.back(), m->ymu.p,
+                         m->ysd.p);
+      MCHK(hipGetLastError());
+    }
     return GP_OK;
   });
 }

@@ -22,7 +22,7 @@ GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ESTATE = -1, -2, -3, -4
 EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "dispatch_objective", "plan_step",
            "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_tuning",
            "plan_nn_rows", "plan_features", "plan_targets", "plan_start_from_prediction",
-           "mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
+           "mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward", "mlp_forward_noalloc",
            "mlp_loss_grad", "mlp_adam_step", "mlp_fit_scaling", "mlp_get_scaling",
            "mlp_set_scaling", "mlp_time_forward", "mlp_gemm_test", "mlp_free", "mlp_last_error",
            "plan_sizes", "plan_free", "plan_last_error")
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH):
     lib.mlp_get_params.argtypes = [C.c_void_p, P(C.c_float)]
     lib.mlp_set_params.argtypes = [C.c_void_p, P(C.c_float)]
     lib.mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    lib.mlp_forward_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, P(C.c_int64)]
+    lib.mlp_forward_noalloc.restype = C.c_int
     lib.mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                   P(C.c_double), P(C.c_float)]
     lib.mlp_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_double,
@@ -443,6 +445,24 @@ class MLP:
         assert ydev == dev
         self._check(self.lib.mlp_forward(self.h, xp, rows, dev, yp))
         return Y
+
+    def forward_noalloc(self, X, Y):
+        """mlp_forward_noalloc on contiguous float32 CUDA tensors X
+        [rows x n_in] and Y [rows x n_out]; enqueued on the network's
+        stream, no synchronisation.  Returns the library's row limit."""
+        _check_dev(X)
+        _check_dev(Y)
+        cap = C.c_int64()
+        self._check(self.lib.mlp_forward_noalloc(self.h, C.c_void_p(X.data_ptr()), int(X.shape[0]),
+                                                 C.c_void_p(Y.data_ptr()), C.byref(cap)))
+        return int(cap.value)
+
+    def noalloc_rows(self):
+        """The row limit of mlp_forward_noalloc for this network (a call with
+        NULL buffers fails validation after reporting it)."""
+        cap = C.c_int64()
+        self.lib.mlp_forward_noalloc(self.h, None, 1, None, C.byref(cap))
+        return int(cap.value)
 
     def loss_grad(self, X, T):
         Xk, xp, dev = self._arg(X)
