@@ -565,6 +565,93 @@ def plan_warm_leg(args):
     print(json.dumps(out), flush=True)
 
 
+def key_days_leg(args):
+    """The paper's key-day study (Section 3.1, Fig. 2 analogue) on a synthetic
+    360-day year of the 100-node stand-in at 200 $/t: projected SGD with
+    batches of B = 8 days sampled from 16 key days (top 4 peak load, peak net
+    load, peak renewable and lowest renewable days) or from all 360 days,
+    the same number of steps for both, every run's plan scored on all 360
+    days (out of sample for the key-day run) every `--kd-eval` steps."""
+    import numpy as np
+    import torch
+
+    from paper_2410_13055_amd import cases, gridplan
+
+    case = cases.year()
+    S = len(case.scenarios)
+    full = list(range(S))
+    lo, hi = case.eta_min(), case.eta_max()
+    gamma = case.gamma()
+    omega = case.omega
+    keyd = cases.key_days(case, lo)
+    log = lambda *a: print("[key-days]", *a, file=sys.stderr, flush=True)  # noqa: E731
+    plan = gridplan.Plan(case, gridplan.options(block=256, variant=1, check_every=64),
+                         stream=gridplan.current_stream())
+    fails = {"eval": 0, "step": 0}
+
+    def phi_full(eta):
+        _, st, rc = plan.solve(eta, full, warm=1)
+        if rc:
+            fails["eval"] += 1
+        return float(gamma @ eta + plan.objective(full, omega, eta=eta))
+
+    plan.solve(lo, keyd[:args.kd_batch], warm=0)
+    g0, _, _ = plan.grad(keyd[:args.kd_batch], omega)
+    alpha = 0.1 * float((hi - lo).min()) / float(np.abs(gamma + g0).max())
+    log(f"key days {keyd}; step size {alpha:.4g}/sqrt(k)")
+
+    def run(pool, seed, label):
+        rng = np.random.default_rng(seed)
+        eta = lo.copy()
+        curve = [(0, phi_full(eta))]
+        t0 = time.perf_counter()
+        for k in range(1, args.kd_steps + 1):
+            scen = sorted(rng.choice(pool, args.kd_batch, replace=False).tolist())
+            eta, _, _, rc = plan.step(alpha / np.sqrt(k), scen, gamma, eta, omega=omega, warm=1)
+            if rc:
+                fails["step"] += 1
+            if k % args.kd_eval == 0:
+                curve.append((k, phi_full(eta)))
+                log(f"{label} step {k}: 360-day objective {curve[-1][1]:.6e}")
+        torch.cuda.synchronize()
+        return eta, curve, time.perf_counter() - t0
+
+    _, ck, tk = run(keyd, 1, "key days")
+    _, cf, tf = run(full, 2, "full year")
+    fk, ff = ck[-1][1], cf[-1][1]
+    out = {"metric": "360-day objective of the plan: key-day SGD vs full-year SGD (lower is better)",
+           "value": round((fk - ff) / fk, 5), "unit": "relative gain of the full-year plan",
+           "config": {"workload": f"year100: {case.networks[0].n_nodes} nodes, {case.networks[0].n_lines} lines, "
+                                  f"{case.networks[0].n_gens} generators, {case.networks[0].n_batt} batteries, "
+                                  f"T=24, {S} daily scenarios, 200 $/t",
+                      "batch": args.kd_batch, "steps": args.kd_steps, "eval_every": args.kd_eval,
+                      "alpha0": alpha, "step_rule": "alpha0 / sqrt(k)", "key_days": keyd},
+           "key_days_curve": ck, "full_year_curve": cf, "key_days_s": round(tk, 1), "full_year_s": round(tf, 1),
+           "unconverged": fails}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+def write_keydays_profile(d):
+    """profiles/key_days_year100.md from <d>/kd.json (the line of
+    `bench.py --key-days`)."""
+    with open(os.path.join(d, "kd.json")) as fh:
+        r = json.loads(next(l for l in fh if l.startswith('{"metric"')))
+    c = r["config"]
+    out = ["# Key days vs the full year (the paper's Section 3.1 study, synthetic stand-in)", "",
+           "Command:", "", "    python bench.py --key-days", "",
+           f"Workload: {c['workload']}; projected SGD, batches of {c['batch']} days, {c['steps']} steps per run, "
+           f"step {c['alpha0']:.4g}/sqrt(k); both plans scored on all days every {c['eval_every']} steps.  Key days "
+           f"(top 4 peak load, peak net load, peak renewable, lowest renewable): {c['key_days']}.", "",
+           "| step | 360-day objective, key-day run | 360-day objective, full-year run |", "|---|---|---|"]
+    for (k, a), (_, b) in zip(r["key_days_curve"], r["full_year_curve"]):
+        out.append(f"| {k} | {a:.6e} | {b:.6e} |")
+    out += ["", f"The full-year plan scores {100 * r['value']:.2f} % lower on the 360 days than the key-day plan "
+            f"(run times {r['key_days_s']} s and {r['full_year_s']} s).  Unconverged solves: {r['unconverged']}."]
+    with open(os.path.join(ROOT, "profiles", "key_days_year100.md"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+
+
 def warm_start_leg(args):
     """s/gradient step on the 1000-node workload, cold vs learned warm (with
     the previous-iterate warm start as the extra baseline).
@@ -916,6 +1003,11 @@ def main():
     ap.add_argument("--pw-omegas", type=float, nargs="+", default=[100.0, 150.0, 250.0, 300.0])
     ap.add_argument("--pw-src", help="file of the 200 $/t plan: read when present, else written")
     ap.add_argument("--pw-src-steps", type=int, default=0, help="steps of the 200 $/t run (default --pw-steps)")
+    ap.add_argument("--key-days", action="store_true",
+                    help="the key-day study: 16 key days vs the full year of the 100-node stand-in")
+    ap.add_argument("--kd-steps", type=int, default=100)
+    ap.add_argument("--kd-eval", type=int, default=25)
+    ap.add_argument("--kd-batch", type=int, default=8)
     ap.add_argument("--mlp", action="store_true",
                     help="time the warm-start network's forward pass on 128,000 rows (its MFMA roofline)")
     ap.add_argument("--warm-start", action="store_true",
@@ -937,6 +1029,8 @@ def main():
             write_mlp_profile(args.summarize)
         if os.path.exists(os.path.join(args.summarize, "ws_bench.json")):
             write_warmstart_profile(args.summarize)
+        if os.path.exists(os.path.join(args.summarize, "kd.json")):
+            write_keydays_profile(args.summarize)
         if os.path.exists(os.path.join(args.summarize, "trace_gap")):
             write_timeline_profile(args.summarize)
         import glob
@@ -964,6 +1058,9 @@ def main():
         return
     if args.plan_warm:
         plan_warm_leg(args)
+        return
+    if args.key_days:
+        key_days_leg(args)
         return
     if args.config == 4 and not args.pmc_run:
         headline_leg(args)

@@ -291,6 +291,66 @@ def geo100(seed=None, S=16) -> Case:
     return _uniform_case("geo100", 5, 100, 417, 42, 24, S, "geo", seed=seed)
 
 
+def year(n_nodes=100, G=417, B=42, days=360, omega=200.0, seed=None) -> Case:
+    """A synthetic year of daily scenarios (T = 24) on a geometric network of
+    the warm-start study's size, for the paper's key-day study (Section 3.1,
+    roughly a full year of days against a handful of key days).  The days
+    differ by season as well as by weather: with y = day / days,
+      load   x (1 + 0.15 cos 2 pi (y - 0.55))   (summer peak; the per-node
+             lognormal level of every day is kept),
+      solar  x (0.75 + 0.25 cos 2 pi (y - 0.47)) (long summer days),
+      wind   x (0.8 + 0.3 cos 2 pi (y - 0.05)), clipped to 1 (windy winters),
+    on top of the same hourly shapes and Beta draws as the other workloads.
+    Capacity boxes are sized on the mean daily peak as elsewhere; gas emits
+    0.4 t/MWh and the carbon weight defaults to 200 $/t (Section 3.1)."""
+    ss = np.random.SeedSequence(9 if seed is None else seed)
+    net_ss, *scen_ss = ss.spawn(days + 1)
+    net_rng = np.random.Generator(np.random.PCG64(net_ss))
+    lf, lt = geometric_mst_plus(net_rng, n_nodes, int(round(1.5 * n_nodes)))
+    kinds = _kinds(net_rng, G)
+    scen, loads = [], []
+    T = 24
+    for d in range(days):
+        rng = np.random.Generator(np.random.PCG64(scen_ss[d]))
+        y = d / days
+        ld = _loads(rng, n_nodes, T) * (1.0 + 0.15 * math.cos(2 * math.pi * (y - 0.55)))
+        av = _avail(rng, kinds, T)
+        av[kinds == SOLAR] *= 0.75 + 0.25 * math.cos(2 * math.pi * (y - 0.47))
+        av[kinds == WIND] = np.minimum(1.0, av[kinds == WIND] * (0.8 + 0.3 * math.cos(2 * math.pi * (y - 0.05))))
+        ld, av = _f32(ld), _f32(av)
+        loads.append(ld)
+        scen.append(Scenario(network=0, T=T, avail=av, load=ld, weight=8760.0 / T))
+    peak = float(np.mean([l.max(axis=1).sum() for l in loads]))
+    net = _network(net_rng, n_nodes, lf, lt, kinds, B, peak)
+    return Case(name=f"year{n_nodes}", networks=[net], scenarios=scen, omega=omega)
+
+
+def key_days(case: Case, eta: np.ndarray, per: int = 4):
+    """The paper's key days (Section 3.1 footnote): the `per` days each of
+    highest peak load, highest peak net load (load minus available
+    renewable capacity at the capacities eta), highest peak renewable
+    availability and lowest renewable energy, taken in that order and
+    skipping days already chosen.  Returns sorted scenario indices."""
+    off = case.eta_offsets()
+    stats = []
+    for sc in case.scenarios:
+        net = case.networks[sc.network]
+        e = eta[off[sc.network]:off[sc.network + 1]]
+        ren = net.gen_cost == 0
+        load = sc.load.sum(axis=0)
+        renew = (sc.avail[ren] * e[:net.n_gens][ren, None]).sum(axis=0)
+        stats.append((load.max(), (load - renew).max(), renew.max(), -renew.sum()))
+    stats = np.array(stats)
+    chosen = []
+    for col in range(4):
+        for s in np.argsort(-stats[:, col], kind="stable"):
+            if len([c for c in chosen if c[1] == col]) >= per:
+                break
+            if int(s) not in [c[0] for c in chosen]:
+                chosen.append((int(s), col))
+    return sorted(c[0] for c in chosen)
+
+
 def config2(seed=None, S=64) -> Case:
     """64 scenarios of uneven shape: each scenario its own network with
     N ~ U{100..500}, L = 1.5N, G = round(4.17N), B = round(0.417N) and

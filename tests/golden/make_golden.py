@@ -24,7 +24,13 @@ stores, as JSON:
   magnitude (congested), 4 batteries.
 
     python tests/golden/make_golden.py 1 0 1      # config 1, scenarios 0 and 1
-    python tests/golden/make_golden.py 3 1        # config 3, scenario 1
+    python tests/golden/make_golden.py 3 1        # config 3, scenario 1 (subset mode)
+
+For the 500-node workload (config 3) a back-solve of the reduced system costs
+seconds, so the differences are taken on 40 stratified candidates only (12
+generators, the 16 lines with the largest gradient magnitude, 12 batteries),
+from which the 20-capacity subset is drawn among the verified ones; the
+per-coordinate arrays then hold NaN / 0 elsewhere.
 
 The interior-point solution of each scenario is cached (uncompressed npz,
 not committed) under tests/golden/.cache/, so the derived values can be
@@ -71,6 +77,20 @@ def _solution(case, cfg, s, qp):
     return sol, False
 
 
+def candidates40(case, grad):
+    """Stratified candidates for the subset mode: 4 generators of each kind,
+    the 16 lines with the largest gradient magnitude, 12 batteries."""
+    net = case.networks[0]
+    G, L = net.n_gens, net.n_lines
+    rng = np.random.default_rng(40)
+    idx = []
+    for kind in (cases.GAS, cases.SOLAR, cases.WIND):
+        idx += [int(v) for v in rng.choice(np.where(net.gen_kind == kind)[0], 4, replace=False)]
+    idx += [int(G + v) for v in np.argsort(-np.abs(grad[G:G + L]))[:16]]
+    idx += [int(G + L + v) for v in rng.choice(net.n_batt, 12, replace=False)]
+    return np.array(idx)
+
+
 def subset20(case, grad, ok):
     """Stratified 20-capacity subset among the coordinates in ``ok``."""
     net = case.networks[0]
@@ -101,8 +121,20 @@ def main():
         t_solve = time.time() - t0
         res = D.kkt_residual(qp, sol.x, sol.y)
         gr = Gm.scenario_gradient(qp, sol, case.omega)
-        fd = Gm.fixed_set_differences(qp, sol, case.omega, h=FD_H)
-        wide = Gm.fixed_set_differences(qp, sol, case.omega, h=WIDE_H)
+        subset_mode = cfg == 3
+        js = candidates40(case, gr["grad"]) if subset_mode else None
+        fd_s = Gm.fixed_set_differences(qp, sol, case.omega, h=FD_H, js=js)
+        wide_s = Gm.fixed_set_differences(qp, sol, case.omega, h=WIDE_H, js=js)
+
+        def full(vals, fill):
+            if not subset_mode:
+                return np.asarray(vals)
+            out = np.full(qp.K, fill, dtype=np.asarray(vals).dtype)
+            out[js] = vals
+            return out
+        fd = {k: full(fd_s[k], np.nan if k in ("central", "dist", "curv") else False)
+              for k in ("central", "ok", "dist", "curv")}
+        wide = {"ok": full(wide_s["ok"], False)}
         ok = fd["ok"]
         scale = np.abs(gr["grad"]).max()
         agree = float(np.abs(fd["central"][ok] - gr["grad"][ok]).max(initial=0.0) / scale)
@@ -113,6 +145,7 @@ def main():
             "polished": bool(sol.polished), "rank_deficient": bool(gr["rank_deficient"]),
             "grad": [float(v) for v in gr["grad"]],
             "fd_h": FD_H, "fd_central": [float(v) for v in fd["central"]],
+            "fd_candidates": None if js is None else [int(v) for v in js],
             "fd_ok": [int(v) for v in ok], "ok_wide": [int(v) for v in wide["ok"]], "wide_h": WIDE_H,
             "kink_distance": [float(v) for v in fd["dist"]], "curvature": [float(v) for v in fd["curv"]],
             "fd_vs_grad_max_rel": agree,

@@ -58,3 +58,34 @@ def test_generated_values_respect_their_ranges():
                 seen.add(m)
                 stack.append(m)
     assert len(seen) == n.n_nodes
+
+
+def test_key_days_follow_their_definition():
+    """Key days (Section 3.1 footnote): 4 days each of highest peak load,
+    highest peak net load, highest peak renewable availability and lowest
+    renewable energy, distinct, 16 in all; a year has seasons (summer load
+    above winter load on average)."""
+    cs = cases.year(n_nodes=12, G=30, B=3, days=48)
+    eta = cs.eta_min()
+    kd = cases.key_days(cs, eta)
+    assert len(kd) == 16 == len(set(kd))
+    net = cs.networks[0]
+    ren = net.gen_cost == 0
+    load = np.array([sc.load.sum(0) for sc in cs.scenarios])
+    renew = np.array([(sc.avail[ren] * eta[:net.n_gens][ren, None]).sum(0) for sc in cs.scenarios])
+    # the four highest peak-load days are always chosen (their criterion goes first)
+    assert set(np.argsort(-load.max(1))[:4].tolist()) <= set(kd)
+    # every criterion has at least its four best days among the chosen or
+    # already taken by an earlier criterion
+    for col in ((load - renew).max(1), renew.max(1), -renew.sum(1)):
+        best = np.argsort(-col)
+        k = 0
+        for s in best:
+            if s in kd:
+                k += 1
+            if k == 4:
+                break
+        assert k == 4
+    mid = [d for d in range(48) if 18 <= d < 30]
+    ends = [d for d in range(48) if d < 6 or d >= 42]
+    assert load[mid].mean() > load[ends].mean()

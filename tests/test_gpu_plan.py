@@ -108,6 +108,11 @@ def test_full_size_against_stored_oracle(cfg, s, bar):
               flush=True)
         assert arith <= 1e-9
     ok = np.array(gd["fd_ok"], bool)
+    if gd.get("fd_candidates"):
+        # subset mode: only the candidates were verified; the others count
+        ok = np.ones_like(ok)
+        cand = np.array(gd["fd_candidates"])
+        ok[cand] = np.array(gd["fd_ok"], bool)[cand]
     err = np.linalg.norm((g - ref)[ok]) / np.linalg.norm(ref[ok])
     big = ok & (np.abs(ref) > 1e-2 * np.abs(ref).max())
     per = np.abs(g - ref)[big] / np.abs(ref)[big]
@@ -122,7 +127,7 @@ def test_full_size_against_stored_oracle(cfg, s, bar):
         with np.errstate(divide="ignore", invalid="ignore"):
             bound = w * (G / dist + 0.5 * curv * np.where(np.isfinite(dist), dist, 0.0))
         slack = 1e-7 * np.abs(ref).max()
-        viol = ok & (np.abs(g - ref) > bound + slack)
+        viol = ok & np.isfinite(bound) & (np.abs(g - ref) > bound + slack)
         assert not viol.any(), np.where(viol)[0][:10]
 
 
@@ -263,3 +268,33 @@ def test_adjoint_solves_along_a_carbon_priced_planning_path_converge():
             eta = np.clip(eta - alpha / np.sqrt(k) * (gamma + g), lo, hi)
             if k % 5 == 0:
                 p.solve(eta, pool, warm=1)
+
+
+@pytest.mark.parametrize("s", [0, 1])
+def test_config3_autograd_against_differences_on_the_subset(s):
+    """500-node workload at 50 $/t (h includes emissions, so the gradient
+    needs the adjoint solve): CapacityCost.apply's gradient against the
+    stored central differences (h = 1e-3 MW, fixed-active-set re-solves
+    verified at both ends) and the oracle gradient on the stratified
+    20-capacity subset.  Solved to 1e-5: at 1e-4 one congested line's entry
+    of the subset is off by about 1 %."""
+    import torch
+
+    from paper_2410_13055_amd.autograd import CapacityCost
+    gd = _golden(3, s)
+    case = cases.by_id(3)
+    eta0 = _golden_eta(case)
+    sub = np.array(gd["subset20"])
+    w = case.scenarios[s].weight
+    with _plan(case, tol=1e-5, max_iter=2_000_000) as p:
+        eta = torch.tensor(eta0, dtype=torch.float64, requires_grad=True)
+        h = CapacityCost.apply(eta, p, [s], case.omega)
+        h.backward()
+        g = eta.grad.numpy()
+    fd = w * np.array(gd["fd_central"])[sub]
+    ref = w * np.array(gd["grad"])[sub]
+    e_fd = np.linalg.norm(g[sub] - fd) / np.linalg.norm(fd)
+    e_or = np.linalg.norm(g[sub] - ref) / np.linalg.norm(ref)
+    print(f"[gpu] config 3 scenario {s}: subset gradient vs differences {e_fd:.2e}, vs oracle {e_or:.2e}", flush=True)
+    assert abs(h.item() - w * gd["h"]) <= 1e-4 * abs(w * gd["h"])
+    assert e_fd <= 1e-3 and e_or <= 1e-3
