@@ -13,6 +13,7 @@ t = 0..T-1, 1 h steps):
 variables (canonical order, each block [device][hour])
     p   [G,T]  generator output            0 <= p <= avail[g,t] * eta_g
     f   [L,T]  line flow, from -> to        -eta_l <= f <= eta_l
+               (the last n_hvdc lines are HVDC links, the rest AC lines)
     th  [N,T]  bus voltage angle            free
     ch  [B,T]  battery charge               0 <= ch <= eta_k
     dis [B,T]  battery discharge            0 <= dis <= eta_k
@@ -22,7 +23,10 @@ variables (canonical order, each block [device][hour])
 equalities (canonical order; duals y = [pi | mu | nu])
     balance [N,T]: sum_{g at n} p + sum_{k at n} (dis - ch) + u
                    + sum_{l: to(l)=n} f - sum_{l: from(l)=n} f = D[n,t]
-    flow    [L,T]: f - beta_l (th[from(l)] - th[to(l)]) = 0     (DC power flow)
+    flow    [L_ac,T]: f - beta_l (th[from(l)] - th[to(l)]) = 0  (DC power flow,
+                   AC lines l < L_ac only; an HVDC link's flow is a free
+                   transfer within its capacity, so it enters the two
+                   balance rows and nothing else)
     soc     [B,T]: soc[t] - soc[t-1] - eff * ch[t] + dis[t] = 0, cyclic in t
 
 objective
@@ -109,11 +113,12 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
     sc = case.scenarios[s]
     net = case.networks[sc.network]
     G, L, N, B, T = net.n_gens, net.n_lines, net.n_nodes, net.n_batt, sc.T
+    Lac = L - int(getattr(net, "n_hvdc", 0))
     K = net.K
     eta_net = np.asarray(eta_net, dtype=np.float64)
     assert eta_net.shape == (K,)
     vs = block_slices(G, L, N, B, T)
-    rs = row_slices(N, L, B, T)
+    rs = row_slices(N, Lac, B, T)
     n, m = vs["n"], rs["m"]
     t = np.arange(T)
 
@@ -138,10 +143,11 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
     put(ridx("bal", np.arange(N)), vidx("u", np.arange(N)), 1.0)
     put(ridx("bal", net.line_to), vidx("f", np.arange(L)), 1.0)
     put(ridx("bal", net.line_from), vidx("f", np.arange(L)), -1.0)
-    # flow rows: f - beta (th_from - th_to) = 0
-    put(ridx("flow", np.arange(L)), vidx("f", np.arange(L)), 1.0)
-    put(ridx("flow", np.arange(L)), vidx("th", net.line_from), -net.line_beta[:, None])
-    put(ridx("flow", np.arange(L)), vidx("th", net.line_to), net.line_beta[:, None])
+    # flow rows of the AC lines: f - beta (th_from - th_to) = 0
+    ac = np.arange(Lac)
+    put(ridx("flow", ac), vidx("f", ac), 1.0)
+    put(ridx("flow", ac), vidx("th", net.line_from[:Lac]), -net.line_beta[:Lac, None])
+    put(ridx("flow", ac), vidx("th", net.line_to[:Lac]), net.line_beta[:Lac, None])
     # soc rows: soc[t] - soc[t-1] - eff ch[t] + dis[t] = 0 (cyclic)
     kb = np.arange(B)
     put(ridx("soc", kb), vidx("soc", kb), 1.0)
@@ -198,7 +204,7 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
 
     return QP(E=E, e=e, q=q, lo=lo, hi=hi, r=float(case.r), hi_idx=hi_idx, hi_coef=hi_coef,
               lo_idx=lo_idx, lo_coef=lo_coef, emis=emis, fuel=fuel,
-              dims=dict(G=G, L=L, N=N, B=B, T=T, vs=vs, rs=rs), K=K)
+              dims=dict(G=G, L=L, Lac=Lac, N=N, B=B, T=T, vs=vs, rs=rs), K=K)
 
 
 # --------------------------------------------------------------------------

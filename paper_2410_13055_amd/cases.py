@@ -57,10 +57,15 @@ class Network:
     eta_min: np.ndarray     # float64 [K]
     eta_max: np.ndarray     # float64 [K]
     gamma: np.ndarray       # float64 [K] $/MW-yr investment cost
+    n_hvdc: int = 0         # the last n_hvdc lines are HVDC links (their beta is unused)
 
     @property
     def n_lines(self) -> int:
         return int(self.line_from.shape[0])
+
+    @property
+    def n_ac(self) -> int:
+        return self.n_lines - int(self.n_hvdc)
 
     @property
     def n_gens(self) -> int:
@@ -234,8 +239,26 @@ def storage_gamma_per_mw(price_per_kwh: float, hours: float = HOURS,
 # configurations
 # --------------------------------------------------------------------------
 
+def hvdc_links(seed, n_nodes, lf, lt, n_hvdc):
+    """``n_hvdc`` HVDC links between distinct node pairs that no AC line
+    joins (long-distance links in the paper's 500-node case, Section 3.1),
+    drawn from their own stream so the AC part of a case does not change."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 0x4456])))
+    used = {(min(a, b), max(a, b)) for a, b in zip(lf.tolist(), lt.tolist())}
+    hf, ht = [], []
+    while len(hf) < n_hvdc:
+        a, b = (int(v) for v in rng.choice(n_nodes, 2, replace=False))
+        if (min(a, b), max(a, b)) in used:
+            continue
+        used.add((min(a, b), max(a, b)))
+        hf.append(a)
+        ht.append(b)
+    return (np.concatenate([lf, np.array(hf, np.int32)]).astype(np.int32),
+            np.concatenate([lt, np.array(ht, np.int32)]).astype(np.int32))
+
+
 def _uniform_case(name, cfg_id, n_nodes, G, B, T, S, topo, omega=0.0,
-                  fixed_counts=None, storage_price=None, seed=None):
+                  fixed_counts=None, storage_price=None, seed=None, n_hvdc=0):
     ss = np.random.SeedSequence(cfg_id if seed is None else seed)
     net_ss, *scen_ss = ss.spawn(S + 1)
     net_rng = np.random.Generator(np.random.PCG64(net_ss))
@@ -243,6 +266,8 @@ def _uniform_case(name, cfg_id, n_nodes, G, B, T, S, topo, omega=0.0,
         lf, lt = ring_with_chords(n_nodes)
     else:
         lf, lt = geometric_mst_plus(net_rng, n_nodes, int(round(1.5 * n_nodes)))
+    if n_hvdc:
+        lf, lt = hvdc_links(cfg_id if seed is None else seed, n_nodes, lf, lt, n_hvdc)
     kinds = _kinds(net_rng, G, fixed_counts)
     scen = []
     loads = []
@@ -255,6 +280,7 @@ def _uniform_case(name, cfg_id, n_nodes, G, B, T, S, topo, omega=0.0,
     peak = float(np.mean([l.max(axis=1).sum() for l in loads]))
     sg = None if storage_price is None else storage_gamma_per_mw(storage_price)
     net = _network(net_rng, n_nodes, lf, lt, kinds, B, peak, sg)
+    net.n_hvdc = int(n_hvdc)
     return Case(name=name, networks=[net], scenarios=scen, omega=omega)
 
 
@@ -374,11 +400,21 @@ def config2(seed=None, S=64) -> Case:
     return Case(name="uneven64", networks=nets, scenarios=scens)
 
 
-def small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, omega=0.0) -> Case:
+def small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, omega=0.0, n_hvdc=0) -> Case:
     """A small geometric case (for quick parity tests): several tiles of
-    work per class and a ragged tail at any block size."""
-    return _uniform_case(f"geo{n_nodes}", 100, n_nodes, G, B, T, S, "geo",
-                         omega=omega, seed=seed)
+    work per class and a ragged tail at any block size.  With n_hvdc > 0
+    that many HVDC links are added after the AC lines."""
+    return _uniform_case(f"geo{n_nodes}" + (f"_hvdc{n_hvdc}" if n_hvdc else ""), 100, n_nodes, G, B, T, S,
+                         "geo", omega=omega, seed=seed, n_hvdc=n_hvdc)
+
+
+def hvdc_two_node(cA=20.0, cB=60.0, PA=300.0, PB=200.0, D=150.0, F=80.0):
+    """two_node with the line replaced by an HVDC link 0 -> 1 of capacity F:
+    the flow is a free choice within [-F, F] and no angle enters."""
+    cs = two_node(cA=cA, cB=cB, PA=PA, PB=PB, D=D, F=F)
+    cs.networks[0].n_hvdc = 1
+    cs.name = "hvdc_two_node"
+    return cs
 
 
 def two_node(cA=20.0, cB=60.0, PA=300.0, PB=200.0, D=150.0, F=80.0, beta=10.0, T=1):
