@@ -50,7 +50,7 @@ def algorithmic_bytes(case, scen):
         n = case.networks[sc.network]
         T = sc.T
         nx += (n.n_gens + n.n_lines + 2 * n.n_nodes + 3 * n.n_batt) * T
-        ny += (n.n_nodes + n.n_lines + n.n_batt) * T
+        ny += (n.n_nodes + n.n_ac + n.n_batt) * T
         gt += n.n_gens * T
         nt += n.n_nodes * T
     return dict(primal=12 * nx + 12 * ny + 4 * gt, dual=4 * nx + 8 * ny + 4 * nt, n_x=nx, n_y=ny)
@@ -67,7 +67,7 @@ def sec8d_bytes(case, scen):
         n = case.networks[sc.network]
         T = sc.T
         nx = (n.n_gens + n.n_lines + 2 * n.n_nodes + 3 * n.n_batt) * T
-        ny = (n.n_nodes + n.n_lines + n.n_batt) * T
+        ny = (n.n_nodes + n.n_ac + n.n_batt) * T
         tot += 8 * nx + 8 * ny + 4 * (n.n_gens + n.n_nodes) * T
     return tot
 

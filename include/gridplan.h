@@ -13,21 +13,25 @@
  *
  * Dispatch model of one scenario (hours t = 0..T-1, 1 h each):
  *   p[g,t] in [0, avail[g,t] * eta_g]     generator output
- *   f[l,t] in [-eta_l, eta_l]             line flow from -> to
+ *   f[l,t] in [-eta_l, eta_l]             line flow from -> to (AC line or
+ *                                         HVDC link, Section 3.1)
  *   th[n,t] free                          bus angle
  *   ch[k,t], dis[k,t] in [0, eta_k]       battery charge / discharge
  *   soc[k,t] in [0, hours * eta_k]        battery state of charge
  *   u[n,t] >= 0                           unserved load
  *   balance: sum_{g@n} p + sum_{k@n}(dis - ch) + u + sum_{l:to=n} f
  *            - sum_{l:from=n} f = load[n,t]             (dual: price pi)
- *   flow:    f - beta_l (th[from] - th[to]) = 0         (dual: mu)
+ *   flow:    f - beta_l (th[from] - th[to]) = 0         (dual: mu; AC
+ *            lines only: an HVDC link's flow enters its two balance rows
+ *            and is otherwise free within its capacity)
  *   soc:     soc[t] - soc[t-1] - eff ch[t] + dis[t] = 0, cyclic (dual: nu)
  *   c_s(x) = sum cost_g p + lambda_u sum u + (r/2) ||x||^2
  *   h_s(x) = c_s(x) + omega * sum emis_g p   (emissions-aware planning)
  *
  * Canonical per-scenario vector orders (used by the accessors):
  *   x = [p (G*T) | f (L*T) | th (N*T) | ch (B*T) | dis (B*T) | soc (B*T) | u (N*T)]
- *   y = [pi (N*T) | mu (L*T) | nu (B*T)], every block [device][hour].
+ *   y = [pi (N*T) | mu (L_ac*T) | nu (B*T)], every block [device][hour],
+ *   with L_ac = n_lines - n_hvdc (the AC lines come first).
  * Capacity vector per network: eta = [generators | lines | batteries];
  * across networks the vectors are concatenated in network order (K total).
  *
@@ -66,7 +70,7 @@ typedef struct {
   int32_t n_nodes, n_lines, n_gens, n_batt;
   const int32_t* line_from;  /* [n_lines] node index in [0, n_nodes) */
   const int32_t* line_to;    /* [n_lines] node index, != line_from */
-  const double* line_beta;   /* [n_lines] susceptance, > 0 */
+  const double* line_beta;   /* [n_lines] susceptance, > 0 (AC lines) */
   const int32_t* gen_node;   /* [n_gens] */
   const double* gen_cost;    /* [n_gens] marginal cost, $/MWh, >= 0 */
   const double* gen_emis;    /* [n_gens] emission rate, t/MWh, >= 0 */
@@ -74,6 +78,9 @@ typedef struct {
   const double* eta_min;     /* [n_gens + n_lines + n_batt], >= 0; battery
                                 entries > 0 (dispatch_grad) */
   const double* eta_max;     /* [n_gens + n_lines + n_batt], >= eta_min */
+  int32_t n_hvdc;            /* in [0, n_lines]: the last n_hvdc lines are HVDC
+                                links (no power-flow row, no angle coupling;
+                                their line_beta is not read) */
 } gp_network;
 
 /* One operating scenario (Section 2.1: each scenario s has its own cost and

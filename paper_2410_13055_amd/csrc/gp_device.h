@@ -70,7 +70,9 @@ struct NetDev {
   int32_t tptr_off;  // into term_ptr (N+1 entries)
   int32_t aptr_off;  // into ang_ptr (N+1 entries)
   int32_t eta_off;   // into eta (K_net entries: gens, lines, batteries)
-  int32_t pad;
+  int32_t Lac;       // AC lines [0, Lac) have a flow row; lines [Lac, L) are
+                     // HVDC links: their flow-row slots stay zero, and their
+                     // susceptance is stored as 0 so no angle sees them
 };
 
 // terminal codes of the nodal-balance CSR: (index << 2) | type

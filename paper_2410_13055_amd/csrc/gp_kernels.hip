@@ -467,15 +467,16 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
     case VC_LINE: {
       const int l = i / T, t = i - l * T;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-      double pto[4], pfr[4], mu[4];
+      double pto[4], pfr[4], mu[4] = {0.0, 0.0, 0.0, 0.0};
       ldy4(a, yb + (int64_t)to * TT + t, pto);
       ldy4(a, yb + (int64_t)fr * TT + t, pfr);
-      ldy4(a, yf + i, mu);
+      const bool ac = l < nt.Lac;  // an HVDC link has no flow-row copy
+      if (ac) ldy4(a, yf + i, mu);
 #pragma unroll
       for (int k = 0; k < 4; ++k) ey[k] = pto[k] - pfr[k] + mu[k];
       const float cap = a.eta[nt.eta_off + nt.G + l];
       const f4 hi = {cap, cap, cap, cap};
-      upd4(u, (int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + a.cwf[s] * a.w.wf, -hi, hi);
+      upd4(u, (int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -hi, hi);
       break;
     }
     case VC_NODE: {
@@ -563,9 +564,11 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
     case VC_LINE: {
       const int l = i / T, t = i - l * T;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-      const double ey = ldy(a, yb + (int64_t)to * TT + t) - ldy(a, yb + (int64_t)fr * TT + t) + ldy(a, yf + i);
+      const bool ac = l < nt.Lac;
+      const double ey = ldy(a, yb + (int64_t)to * TT + t) - ldy(a, yb + (int64_t)fr * TT + t) +
+                        (ac ? ldy(a, yf + i) : 0.0);
       const float cap = a.eta[nt.eta_off + nt.G + l];
-      u((int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + a.cwf[s] * a.w.wf, -cap, cap);
+      u((int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -cap, cap);
       break;
     }
     case VC_NODE: {
@@ -829,12 +832,14 @@ __global__ __launch_bounds__(BS) void k_check_vars(Args a) {
       case VC_LINE: {
         const int l = i / T, t = i - l * T;
         const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-        const double ey = (double)yb[(int64_t)to * TT + t] - (double)yb[(int64_t)fr * TT + t] + (double)yf[i];
+        const bool ac = l < nt.Lac;
+        const double ey = (double)yb[(int64_t)to * TT + t] - (double)yb[(int64_t)fr * TT + t] + (ac ? yf[i] : 0.0);
         const double cap = a.eta[nt.eta_off + nt.G + l];
         const int64_t idx = (int64_t)nt.G * TT + i;
         double lo = -cap, hi = cap;
         bnd(idx, lo, hi);
-        var_stats(v, xh[idx], x0[idx], ey, 0.0, r, lo, hi, 2.0 * a.w.wb + (double)a.cwf[s] * a.w.wf);
+        var_stats(v, xh[idx], x0[idx], ey, 0.0, r, lo, hi,
+                  2.0 * a.w.wb + (ac ? (double)a.cwf[s] * a.w.wf : 0.0));
         break;
       }
       case VC_NODE: {
@@ -1053,12 +1058,13 @@ __global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb
   } else if (dev < nt.G + nt.L) {
     const int l = dev - nt.G;
     const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
+    const bool ac = l < nt.Lac;
     for (int t = lane; t < T; t += W) {
       const int64_t idx = (int64_t)nt.G * TT + (int64_t)l * TT + t;
       const uint8_t m = am[idx];
       if (m) {
         const double z = (double)yb[(int64_t)to * TT + t] - (double)yb[(int64_t)fr * TT + t] +
-                         (double)yf[(int64_t)l * TT + t] - r * (double)xh[idx];
+                         (ac ? (double)yf[(int64_t)l * TT + t] : 0.0) - r * (double)xh[idx];
         acc += (m & 2) ? -z : z;
       }
     }
@@ -1139,8 +1145,8 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
         else if (v <= -cap) b = 1;
       } else {  // zero capacity: the side the flow would take
         const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-        const double z = yb[(int64_t)to * TT + t] - yb[(int64_t)fr * TT + t] +
-                         yb[(int64_t)nt.N * TT + (int64_t)l * TT + t] - (double)a.r * (double)v;
+        const double mu = l < nt.Lac ? yb[(int64_t)nt.N * TT + (int64_t)l * TT + t] : 0.0;
+        const double z = yb[(int64_t)to * TT + t] - yb[(int64_t)fr * TT + t] + mu - (double)a.r * (double)v;
         b = z > 0.0 ? 2 : 1;
       }
       m[idx] = b;

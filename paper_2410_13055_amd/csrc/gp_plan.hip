@@ -116,6 +116,7 @@ bool finite(double v) { return std::isfinite(v); }
 
 struct NetHost {
   int N, L, G, B;
+  int Lac;          // AC lines (the rest are HVDC links)
   int64_t eta_off;  // global capacity offset
   std::vector<double> eta_min, eta_max;
 };
@@ -127,6 +128,8 @@ struct ScenHost {
   double e2;    // ||load||_2
   double q2;    // ||q||_2
   int64_t xoff, yoff, nx, ny;
+  int64_t ny_out;   // canonical dual length (N + Lac + B) T; the device
+                    // block keeps a zero slot per HVDC link-hour
 };
 
 }  // namespace
@@ -260,7 +263,8 @@ void validate_case(const gp_case_desc* cs) {
   if (!(cs->hours > 0) || !finite(cs->hours)) fail(GP_EINVAL, "hours must be > 0");
   for (int k = 0; k < cs->n_networks; ++k) {
     const gp_network& n = cs->networks[k];
-    if (n.n_nodes < 1 || n.n_lines < 0 || n.n_gens < 0 || n.n_batt < 0)
+    if (n.n_nodes < 1 || n.n_lines < 0 || n.n_gens < 0 || n.n_batt < 0 || n.n_hvdc < 0 ||
+        n.n_hvdc > n.n_lines)
       fail(GP_EINVAL, "network %d: bad counts", k);
     if ((n.n_lines && (!n.line_from || !n.line_to || !n.line_beta)) ||
         (n.n_gens && (!n.gen_node || !n.gen_cost || !n.gen_emis)) || (n.n_batt && !n.batt_node) ||
@@ -270,7 +274,7 @@ void validate_case(const gp_case_desc* cs) {
       if (n.line_from[l] < 0 || n.line_from[l] >= n.n_nodes || n.line_to[l] < 0 ||
           n.line_to[l] >= n.n_nodes || n.line_from[l] == n.line_to[l])
         fail(GP_EINVAL, "network %d line %d: bad endpoints", k, l);
-      if (!(n.line_beta[l] > 0) || !finite(n.line_beta[l]))
+      if (l < n.n_lines - n.n_hvdc && (!(n.line_beta[l] > 0) || !finite(n.line_beta[l])))
         fail(GP_EINVAL, "network %d line %d: susceptance must be > 0", k, l);
     }
     for (int g = 0; g < n.n_gens; ++g) {
@@ -347,16 +351,19 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     d.tptr_off = (int32_t)term_ptr.size();
     d.aptr_off = (int32_t)ang_ptr.size();
     d.eta_off = (int32_t)eta_off;
+    d.Lac = n.n_lines - n.n_hvdc;
     for (int g = 0; g < d.G; ++g) {
       gen_node.push_back(n.gen_node[g]);
       gen_cost.push_back((float)n.gen_cost[g]);
       gen_emis.push_back((float)n.gen_emis[g]);
       qinf = std::max(qinf, n.gen_cost[g]);
     }
+    // an HVDC link's susceptance is stored as zero: the angle terms of the
+    // sweeps then see no coupling through it
     for (int l = 0; l < d.L; ++l) {
       line_from.push_back(n.line_from[l]);
       line_to.push_back(n.line_to[l]);
-      line_beta.push_back((float)n.line_beta[l]);
+      line_beta.push_back(l < d.Lac ? (float)n.line_beta[l] : 0.f);
     }
     for (int b = 0; b < d.B; ++b) batt_node.push_back(n.batt_node[b]);
     // node -> terminals (balance rows) and node -> incident lines (angles)
@@ -369,7 +376,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
       tl[n.line_from[l]].push_back((l << 2) | TT_LINE_FROM);
       al[n.line_to[l]].push_back(l << 1);
       al[n.line_from[l]].push_back((l << 1) | 1);
-      const double bb = (double)(float)n.line_beta[l];
+      const double bb = l < d.Lac ? (double)(float)n.line_beta[l] : 0.0;
       b2[n.line_to[l]] += bb * bb;
       b2[n.line_from[l]] += bb * bb;
     }
@@ -393,6 +400,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     nh.L = d.L;
     nh.G = d.G;
     nh.B = d.B;
+    nh.Lac = d.Lac;
     nh.eta_off = eta_off;
     const int Kn = d.G + d.L + d.B;
     nh.eta_min.assign(n.eta_min, n.eta_min + Kn);
@@ -474,6 +482,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     sh.yoff = yoff;
     sh.nx = nx;
     sh.ny = ny;
+    sh.ny_out = (int64_t)(n.N + n.Lac + n.B) * sc.T;
     p->scen.push_back(sh);
     p->max_T = std::max(p->max_T, sc.T);
     xoff += (nx + 3) / 4 * 4;
@@ -642,7 +651,7 @@ void build_sweep_tiles(gp_plan* p, const std::vector<int>& subset) {
     adds(svt, VC_NODE, (int64_t)n.N * T);
     adds(svt, VC_BATT, (int64_t)n.B * T);
     adds(srt, RC_BAL, (int64_t)n.N * T);
-    adds(srt, RC_FLOW, (int64_t)n.L * T);
+    adds(srt, RC_FLOW, (int64_t)n.Lac * T);  // AC lines only
     // battery chains: T/4 threads per chain, as many chains per block as fit
     const int cpb = v4 ? bs / (T / 4) : 0;
     if (cpb > 0)
@@ -687,7 +696,7 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
     add(vt, VC_NODE, (int64_t)n.N * T);
     add(vt, VC_BATT, (int64_t)n.B * T);
     add(rt, RC_BAL, (int64_t)n.N * T);
-    add(rt, RC_FLOW, (int64_t)n.L * T);
+    add(rt, RC_FLOW, (int64_t)n.Lac * T);
     for (int k = 0; k < n.B; ++k) rt.push_back(Tile{s, RC_SOC, k, 1});
     ranges.push_back(v0);
     ranges.push_back((int)vt.size());
@@ -1417,12 +1426,16 @@ int dispatch_get_solution(gp_plan* p, int32_t s, float* x_out, double* y_out, in
     if (s < 0 || s >= p->S) fail(GP_EINVAL, "scenario index out of range");
     const ScenHost& sh = p->scen[s];
     if (n_x) *n_x = sh.nx;
-    if (n_y) *n_y = sh.ny;
+    if (n_y) *n_y = sh.ny_out;
     if ((x_out || y_out) && !p->has_solution[s]) fail(GP_ESTATE, "scenario %d has no solution yet", s);
     if (x_out)
       HIPCHK(hipMemcpyAsync(x_out, p->d_xhat.p + sh.xoff, sh.nx * sizeof(float), hipMemcpyDeviceToHost, p->stream));
-    if (y_out)
-      HIPCHK(hipMemcpyAsync(y_out, p->d_yhat.p + sh.yoff, sh.ny * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    if (y_out) {  // [balance | AC flow rows] then the SOC rows past the link slots
+      const int64_t head = sh.ny_out - (int64_t)p->nets[sh.net].B * sh.T;
+      HIPCHK(hipMemcpyAsync(y_out, p->d_yhat.p + sh.yoff, head * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipMemcpyAsync(y_out + head, p->d_yhat.p + sh.yoff + sh.ny - (sh.ny_out - head),
+                            (sh.ny_out - head) * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    }
     HIPCHK(hipStreamSynchronize(p->stream));
     return GP_OK;
   });
@@ -1437,12 +1450,15 @@ int dispatch_set_start(gp_plan* p, int32_t s, const float* x, const double* y) {
     for (int64_t i = 0; i < sh.nx; ++i)
       if (!std::isfinite(x[i])) fail(GP_EINVAL, "x[%lld] is not finite", (long long)i);
     if (y)
-      for (int64_t i = 0; i < sh.ny; ++i)
+      for (int64_t i = 0; i < sh.ny_out; ++i)
         if (!std::isfinite(y[i])) fail(GP_EINVAL, "y[%lld] is not finite", (long long)i);
     HIPCHK(hipMemcpyAsync(p->d_xhat.p + sh.xoff, x, sh.nx * sizeof(float), hipMemcpyHostToDevice, p->stream));
-    if (y)
-      HIPCHK(hipMemcpyAsync(p->d_yhat.p + sh.yoff, y, sh.ny * sizeof(double), hipMemcpyHostToDevice, p->stream));
-    else if (!p->has_solution[s])
+    if (y) {  // the HVDC link slots between the AC flow rows and the SOC rows stay zero
+      const int64_t head = sh.ny_out - (int64_t)p->nets[sh.net].B * sh.T;
+      HIPCHK(hipMemcpyAsync(p->d_yhat.p + sh.yoff, y, head * sizeof(double), hipMemcpyHostToDevice, p->stream));
+      HIPCHK(hipMemcpyAsync(p->d_yhat.p + sh.yoff + sh.ny - (sh.ny_out - head), y + head,
+                            (sh.ny_out - head) * sizeof(double), hipMemcpyHostToDevice, p->stream));
+    } else if (!p->has_solution[s])
       HIPCHK(hipMemsetAsync(p->d_yhat.p + sh.yoff, 0, sh.ny * sizeof(double), p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
     p->has_solution[s] = 1;

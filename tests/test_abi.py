@@ -65,6 +65,8 @@ def _init(case, opts=None):
     (lambda c: setattr(c, "eff", 1.5), "eff"),
     (lambda c: setattr(c.scenarios[0], "network", 3), "network"),
     (lambda c: c.networks[0].eta_min.__setitem__(-1, 0.0), "battery 1: capacity lower bound"),
+    (lambda c: setattr(c.networks[0], "n_hvdc", c.networks[0].n_lines + 1), "bad counts"),
+    (lambda c: setattr(c.networks[0], "n_hvdc", -1), "bad counts"),
 ])
 def test_plan_init_rejects_bad_case(mutate, needle):
     cs = cases.config0()
@@ -72,6 +74,20 @@ def test_plan_init_rejects_bad_case(mutate, needle):
     rc, msg, _ = _init(cs)
     assert rc == gpb.GP_EINVAL
     assert needle in msg
+
+
+def test_hvdc_link_susceptance_is_not_read():
+    # an HVDC link has no power-flow row: a zero or negative beta on it must
+    # not fail validation (on a host without a GPU the call then fails at
+    # the first device allocation instead)
+    cs = cases.hvdc_two_node()
+    cs.networks[0].line_beta[:] = 0.0
+    rc, msg, _ = _init(cs)
+    assert "susceptance" not in msg
+    cs = cases.two_node()
+    cs.networks[0].line_beta[:] = 0.0
+    rc, msg, _ = _init(cs)
+    assert rc == gpb.GP_EINVAL and "susceptance" in msg
 
 
 @pytest.mark.parametrize("opts,needle", [

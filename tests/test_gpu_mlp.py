@@ -115,9 +115,10 @@ def _plan(case, **kw):
     return gb.Plan(case, gb.options(**kw), stream=gb.current_stream())
 
 
-def test_features_and_targets_match_oracle():
+@pytest.mark.parametrize("n_hvdc", [0, 2])
+def test_features_and_targets_match_oracle(n_hvdc):
     import torch
-    cs = cases.small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7)
+    cs = cases.small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, n_hvdc=n_hvdc)
     eta = cases.jitter(cs.eta_min(), 4, eta_min=cs.eta_min(), eta_max=cs.eta_max())
     with _plan(cs) as p:
         p.solve(eta, [0, 1])
