@@ -26,7 +26,10 @@ equalities (canonical order; duals y = [pi | mu | nu])
     flow    [L_ac,T]: f - beta_l (th[from(l)] - th[to(l)]) = 0  (DC power flow,
                    AC lines l < L_ac only; an HVDC link's flow is a free
                    transfer within its capacity, so it enters the two
-                   balance rows and nothing else)
+                   balance rows and nothing else).  On a network whose
+                   susceptances scale with capacity (Section 2.1's A_s(eta):
+                   an expanded line is parallel circuits of the same kind)
+                   beta_l = line_beta_l * eta_l / eta_min_l.
     soc     [B,T]: soc[t] - soc[t-1] - eff * ch[t] + dis[t] = 0, cyclic in t
 
 objective
@@ -77,6 +80,9 @@ class QP:
     fuel: np.ndarray          # $/MWh per variable excluding the unserved penalty
     dims: dict                # block sizes
     K: int
+    # d beta_l / d eta_l per line (0 where beta does not depend on eta):
+    # the constraint matrix's dependence on the capacities
+    line_dbeta: Optional[np.ndarray] = None
 
     @property
     def n(self):
@@ -145,9 +151,15 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
     put(ridx("bal", net.line_from), vidx("f", np.arange(L)), -1.0)
     # flow rows of the AC lines: f - beta (th_from - th_to) = 0
     ac = np.arange(Lac)
+    beta = np.asarray(net.line_beta[:Lac], np.float64)
+    dbeta = np.zeros(L)
+    if getattr(net, "beta_scales", False):
+        ref = np.asarray(net.eta_min[G:G + Lac], np.float64)
+        dbeta[:Lac] = beta / ref
+        beta = beta * eta_net[G:G + Lac] / ref
     put(ridx("flow", ac), vidx("f", ac), 1.0)
-    put(ridx("flow", ac), vidx("th", net.line_from[:Lac]), -net.line_beta[:Lac, None])
-    put(ridx("flow", ac), vidx("th", net.line_to[:Lac]), net.line_beta[:Lac, None])
+    put(ridx("flow", ac), vidx("th", net.line_from[:Lac]), -beta[:, None])
+    put(ridx("flow", ac), vidx("th", net.line_to[:Lac]), beta[:, None])
     # soc rows: soc[t] - soc[t-1] - eff ch[t] + dis[t] = 0 (cyclic)
     kb = np.arange(B)
     put(ridx("soc", kb), vidx("soc", kb), 1.0)
@@ -204,7 +216,9 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
 
     return QP(E=E, e=e, q=q, lo=lo, hi=hi, r=float(case.r), hi_idx=hi_idx, hi_coef=hi_coef,
               lo_idx=lo_idx, lo_coef=lo_coef, emis=emis, fuel=fuel,
-              dims=dict(G=G, L=L, Lac=Lac, N=N, B=B, T=T, vs=vs, rs=rs), K=K)
+              dims=dict(G=G, L=L, Lac=Lac, N=N, B=B, T=T, vs=vs, rs=rs,
+                        line_from=np.asarray(net.line_from), line_to=np.asarray(net.line_to)), K=K,
+              line_dbeta=dbeta if dbeta.any() else None)
 
 
 # --------------------------------------------------------------------------

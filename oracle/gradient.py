@@ -21,6 +21,14 @@ For h = c (no emissions weight) the fit is exact with w = y*, so
 dl/dx_A = -z_A and the gradient is the envelope-theorem value
 -sum_i a_i z_i (z the box multipliers); that identity is a pin.
 
+When the constraint matrix depends on the capacities (Section 2.1's
+A_s(eta); here a line's susceptance beta_l(eta_l) in its flow rows), the
+perturbed system gains the terms of dE: with G = dE'y,
+    r dx_F - E_F' dy = G_F,   E_F dx_F + E_A dx_A = -dE x,
+and the same adjoint w gives
+    dl/d eta_j (extra) = -w' dE_j x + (1/r) (g - E'w)_F' (dE_j' y)_F,
+which for h = c (w = y, zero residual) is the envelope term -y' dE_j x.
+
 A capacity at zero collapses its boxes to points (a generator with
 eta_g = 0, a line with eta_l = 0).  The map is then one-sided in eta, and
 the derivative returned is the one for increasing capacity: an entry whose
@@ -88,6 +96,29 @@ def eta_from_active(qp: D.QP, dl_dx: np.ndarray, at_lo: np.ndarray, at_hi: np.nd
     return out
 
 
+def matrix_terms(qp: D.QP, x: np.ndarray, y: np.ndarray, w: np.ndarray, res: np.ndarray) -> np.ndarray:
+    """The capacity derivative's terms from dE (module docstring): for an
+    AC line l with d beta_l / d eta_l = b', its flow rows (l, t) hold
+    -beta_l at th[from] and +beta_l at th[to], so
+        -w' dE_l x = b' sum_t w_(l,t) (th_from - th_to),
+        (1/r) res' dE_l' y = -(b' / r) sum_t y_(l,t) (res_th_from - res_th_to)
+    with res = g - E'w (angles are always free)."""
+    d = qp.dims
+    T, Lac, G = d["T"], d["Lac"], d["G"]
+    vs, rs = d["vs"], d["rs"]
+    out = np.zeros(qp.K)
+    if Lac == 0:
+        return out
+    th = x[vs["th"]].reshape(-1, T)
+    rth = res[vs["th"]].reshape(-1, T)
+    lf, lt = d["line_from"][:Lac], d["line_to"][:Lac]
+    wl = w[rs["flow"]].reshape(Lac, T)
+    yl = y[rs["flow"]].reshape(Lac, T)
+    db = qp.line_dbeta[:Lac]
+    out[G:G + Lac] = db * ((wl * (th[lf] - th[lt])).sum(1) - (yl * (rth[lf] - rth[lt])).sum(1) / qp.r)
+    return out
+
+
 def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
     """d h_s(x*(eta)) / d eta for one scenario via the least-squares adjoint.
 
@@ -102,6 +133,9 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
     dl_dx = g - qp.E.T @ w
     grad = eta_from_active(qp, dl_dx, at_lo, at_hi)
     env = eta_from_active(qp, -sol.z, at_lo, at_hi)
+    if qp.line_dbeta is not None:
+        grad += matrix_terms(qp, sol.x, sol.y, w, dl_dx)
+        env += matrix_terms(qp, sol.x, sol.y, sol.y, np.zeros(qp.n))
     # weakly active entries whose bound depends on a capacity make the map kinked
     bscale = 1.0 + np.abs(qp.q).max()
     dep_hi, dep_lo = _dependent(qp)
@@ -130,6 +164,8 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
     (``curv`` = d2h/deta_j2 on the piece)."""
     if not sol.polished:
         raise ValueError("fixed-active-set differences need a polished solution")
+    if qp.line_dbeta is not None:
+        raise NotImplementedError("the reduced system moves with eta when the constraint matrix does")
     K = qp.K
     js = np.arange(K) if js is None else np.asarray(js)
     at_lo, at_hi = sol.active_lo, sol.active_hi

@@ -58,6 +58,7 @@ class Network:
     eta_max: np.ndarray     # float64 [K]
     gamma: np.ndarray       # float64 [K] $/MW-yr investment cost
     n_hvdc: int = 0         # the last n_hvdc lines are HVDC links (their beta is unused)
+    beta_scales: bool = False  # AC susceptance beta_l * eta_l / eta_min_l (parallel circuits)
 
     @property
     def n_lines(self) -> int:
@@ -400,12 +401,24 @@ def config2(seed=None, S=64) -> Case:
     return Case(name="uneven64", networks=nets, scenarios=scens)
 
 
-def small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, omega=0.0, n_hvdc=0) -> Case:
+def small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, omega=0.0, n_hvdc=0, beta_scales=False) -> Case:
     """A small geometric case (for quick parity tests): several tiles of
     work per class and a ragged tail at any block size.  With n_hvdc > 0
-    that many HVDC links are added after the AC lines."""
-    return _uniform_case(f"geo{n_nodes}" + (f"_hvdc{n_hvdc}" if n_hvdc else ""), 100, n_nodes, G, B, T, S,
-                         "geo", omega=omega, seed=seed, n_hvdc=n_hvdc)
+    that many HVDC links are added after the AC lines; with beta_scales the
+    AC susceptances scale with line capacity."""
+    cs = _uniform_case(f"geo{n_nodes}" + (f"_hvdc{n_hvdc}" if n_hvdc else "") + ("_scaled" if beta_scales else ""),
+                       100, n_nodes, G, B, T, S, "geo", omega=omega, seed=seed, n_hvdc=n_hvdc)
+    cs.networks[0].beta_scales = bool(beta_scales)
+    return cs
+
+
+def scaled_two_node(cA=20.0, cB=60.0, PA=300.0, PB=200.0, D=150.0, F=80.0, beta=10.0):
+    """two_node whose line's susceptance scales with its capacity (beta at
+    the capacity's lower bound F)."""
+    cs = two_node(cA=cA, cB=cB, PA=PA, PB=PB, D=D, F=F, beta=beta)
+    cs.networks[0].beta_scales = True
+    cs.name = "scaled_two_node"
+    return cs
 
 
 def hvdc_two_node(cA=20.0, cB=60.0, PA=300.0, PB=200.0, D=150.0, F=80.0):

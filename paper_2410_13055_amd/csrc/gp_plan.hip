@@ -1270,6 +1270,11 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
       p->a_y0.alloc(p->ny_tot);
       p->a_dbar.alloc(p->ny_tot);
       p->a_yhat.alloc(p->ny_tot);
+      // the row slots of HVDC links are never written by a row tile: they
+      // must read as zero (the angle terms multiply them by a zero susceptance)
+      HIPCHK(hipMemsetAsync(p->a_y0.p, 0, p->ny_tot * sizeof(double), st));
+      HIPCHK(hipMemsetAsync(p->a_dbar.p, 0, p->ny_tot * sizeof(float), st));
+      HIPCHK(hipMemsetAsync(p->a_yhat.p, 0, p->ny_tot * sizeof(double), st));
     }
     drop_graph(p);
     std::vector<double> einf(nb, -1.0);
