@@ -23,7 +23,8 @@
  *            - sum_{l:from=n} f = load[n,t]             (dual: price pi)
  *   flow:    f - beta_l (th[from] - th[to]) = 0         (dual: mu; AC
  *            lines only: an HVDC link's flow enters its two balance rows
- *            and is otherwise free within its capacity)
+ *            and is otherwise free within its capacity; beta_l may scale
+ *            with eta_l, see gp_network.beta_scales)
  *   soc:     soc[t] - soc[t-1] - eff ch[t] + dis[t] = 0, cyclic (dual: nu)
  *   c_s(x) = sum cost_g p + lambda_u sum u + (r/2) ||x||^2
  *   h_s(x) = c_s(x) + omega * sum emis_g p   (emissions-aware planning)
@@ -81,6 +82,12 @@ typedef struct {
   int32_t n_hvdc;            /* in [0, n_lines]: the last n_hvdc lines are HVDC
                                 links (no power-flow row, no angle coupling;
                                 their line_beta is not read) */
+  int32_t beta_scales;       /* 0, or 1: the constraint matrix depends on the
+                                capacities (Section 2.1's A_s(eta)): an AC
+                                line's susceptance is line_beta[l] * eta_l /
+                                eta_min_l (an expanded corridor of parallel
+                                circuits), so AC lines need eta_min > 0; the
+                                gradient then includes the matrix terms */
 } gp_network;
 
 /* One operating scenario (Section 2.1: each scenario s has its own cost and

@@ -103,11 +103,14 @@ struct Args {
   int32_t qgrab;       // work-queue form: tiles taken per counter update
   // network data
   const int32_t* gen_node;
+  const int32_t* gen_perm;  // variable sweep's visiting order: generators by node
+  const int32_t* line_perm; // ... and lines by their 'from' node (network-local indices)
   const float* gen_cost;
   const float* gen_emis;
   const int32_t* line_from;
   const int32_t* line_to;
-  const float* line_beta;
+  const float* line_beta;   // susceptance at the current capacities (0 for HVDC links)
+  const float* line_dbeta;  // d beta_l / d eta_l (0 unless the line's susceptance scales)
   const int32_t* batt_node;
   const int32_t* term_ptr;
   const int32_t* term;

@@ -456,27 +456,33 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
   double ey[4];
   switch (tl.cls & 0xff) {
     case VC_GEN: {
-      const int g = i / T, t = i - g * T;
+      // generators are visited in node order (gen_perm), so the balance
+      // duals a block gathers come from few nodes
+      const int gq = i / T, t = i - gq * T;
+      const int g = a.gen_perm[nt.gen_off + gq];
+      const int ig = g * T + t;
       const int n = a.gen_node[nt.gen_off + g];
-      const f4 hi = ld4(a.avail + sc.aoff + i) * a.eta[nt.eta_off + g];
+      const f4 hi = ld4(a.avail + sc.aoff + ig) * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
       ldy4(a, yb + (int64_t)n * TT + t, ey);
-      upd4(u, i, ey, q, a.w.wb, zero, hi);
+      upd4(u, ig, ey, q, a.w.wb, zero, hi);
       break;
     }
     case VC_LINE: {
-      const int l = i / T, t = i - l * T;
+      const int lq = i / T, t = i - lq * T;
+      const int l = a.line_perm[nt.line_off + lq];  // lines in order of their 'from' node
+      const int il = l * T + t;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
       double pto[4], pfr[4], mu[4] = {0.0, 0.0, 0.0, 0.0};
       ldy4(a, yb + (int64_t)to * TT + t, pto);
       ldy4(a, yb + (int64_t)fr * TT + t, pfr);
       const bool ac = l < nt.Lac;  // an HVDC link has no flow-row copy
-      if (ac) ldy4(a, yf + i, mu);
+      if (ac) ldy4(a, yf + il, mu);
 #pragma unroll
       for (int k = 0; k < 4; ++k) ey[k] = pto[k] - pfr[k] + mu[k];
       const float cap = a.eta[nt.eta_off + nt.G + l];
       const f4 hi = {cap, cap, cap, cap};
-      upd4(u, (int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -hi, hi);
+      upd4(u, (int64_t)nt.G * TT + il, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -hi, hi);
       break;
     }
     case VC_NODE: {
@@ -554,21 +560,25 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
   const int64_t ys = yf + (int64_t)nt.L * TT;  // SOC rows
   switch (tl.cls) {
     case VC_GEN: {
-      const int g = i / T, t = i - g * T;
+      const int gq = i / T, t = i - gq * T;
+      const int g = a.gen_perm[nt.gen_off + gq];
+      const int ig = g * T + t;
       const int n = a.gen_node[nt.gen_off + g];
-      const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
+      const float hi = a.avail[sc.aoff + ig] * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
-      u(i, ldy(a, yb + (int64_t)n * TT + t), q, a.w.wb, 0.f, hi);
+      u(ig, ldy(a, yb + (int64_t)n * TT + t), q, a.w.wb, 0.f, hi);
       break;
     }
     case VC_LINE: {
-      const int l = i / T, t = i - l * T;
+      const int lq = i / T, t = i - lq * T;
+      const int l = a.line_perm[nt.line_off + lq];
+      const int il = l * T + t;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
       const bool ac = l < nt.Lac;
       const double ey = ldy(a, yb + (int64_t)to * TT + t) - ldy(a, yb + (int64_t)fr * TT + t) +
-                        (ac ? ldy(a, yf + i) : 0.0);
+                        (ac ? ldy(a, yf + il) : 0.0);
       const float cap = a.eta[nt.eta_off + nt.G + l];
-      u((int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -cap, cap);
+      u((int64_t)nt.G * TT + il, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -cap, cap);
       break;
     }
     case VC_NODE: {
@@ -1012,8 +1022,15 @@ __global__ __launch_bounds__(BS) void k_reset(Args a, int mode) {
 // (xhat, yhat).  One wavefront per device (lanes over hours), FP64.  In
 // adjoint mode the same pass runs on the adjoint solution with the mask of
 // the forward solve.  out: [batch][K_net] at goff[b].
+//
+// Where a line's susceptance depends on its capacity (b' = d beta / d eta),
+// the matrix terms are added: the forward pass -y' dE x =
+// b' sum_t mu_t (th_from - th_to) of the forward point; the adjoint pass
+// b' sum_t (w_t (th_from - th_to) + mu_t (d_from - d_to)) with the adjoint
+// point's flow duals w and angles d (fx, fy: the forward point).
 template <int BS>
-__global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb, int mode_adj) {
+__global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb, int mode_adj, const float* fx,
+                                             const double* fy) {
   constexpr int W = 64;
   const int wid = (blockIdx.x * BS + threadIdx.x) / W;
   const int lane = threadIdx.x % W;
@@ -1066,6 +1083,20 @@ __global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb
         const double z = (double)yb[(int64_t)to * TT + t] - (double)yb[(int64_t)fr * TT + t] +
                          (ac ? (double)yf[(int64_t)l * TT + t] : 0.0) - r * (double)xh[idx];
         acc += (m & 2) ? -z : z;
+      }
+    }
+    const double db = a.line_dbeta[nt.line_off + l];
+    if (db != 0.0) {
+      const float* th = fx + sc.xoff + (int64_t)(nt.G + nt.L) * TT;
+      const double* mu = fy + sc.yoff + (int64_t)nt.N * TT + (int64_t)l * TT;
+      const float* dth = xh + (int64_t)(nt.G + nt.L) * TT;
+      for (int t = lane; t < T; t += W) {
+        const double dt = (double)th[(int64_t)fr * TT + t] - (double)th[(int64_t)to * TT + t];
+        if (mode_adj)
+          acc += db * ((double)yf[(int64_t)l * TT + t] * dt +
+                       mu[t] * ((double)dth[(int64_t)fr * TT + t] - (double)dth[(int64_t)to * TT + t]));
+        else
+          acc += db * mu[t] * dt;
       }
     }
   } else {
@@ -1250,11 +1281,11 @@ hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj,
-                       hipStream_t st) {
+hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj, const float* fx,
+                       const double* fy, hipStream_t st) {
   const int64_t threads = ndev * 64;
   const int nblk = (int)((threads + 255) / 256);
-  hipLaunchKernelGGL(k_grad<256>, dim3(nblk), dim3(256), 0, st, a, goff, nb, mode_adj);
+  hipLaunchKernelGGL(k_grad<256>, dim3(nblk), dim3(256), 0, st, a, goff, nb, mode_adj, fx, fy);
   return hipGetLastError();
 }
 

@@ -26,8 +26,8 @@ hipError_t launch_primal(const Args& a, int bs, int j, int check, hipStream_t st
 hipError_t launch_check(const Args& a, int bs, int nb, hipStream_t st);
 hipError_t launch_reset(const Args& a, int bs, int mode, hipStream_t st);
 hipError_t launch_mask(const Args& a, int bs, uint8_t* mask, hipStream_t st);
-hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj,
-                       hipStream_t st);
+hipError_t launch_grad(const Args& a, const int64_t* goff, int nb, int64_t ndev, int mode_adj, const float* fx,
+                       const double* fy, hipStream_t st);
 hipError_t launch_features(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, int maxN,
                            float* X, hipStream_t st);
 hipError_t launch_targets(const Args& a, const int32_t* bscen, int nb, const int32_t* rowoff, int T, int maxN,
@@ -117,6 +117,8 @@ bool finite(double v) { return std::isfinite(v); }
 struct NetHost {
   int N, L, G, B;
   int Lac;          // AC lines (the rest are HVDC links)
+  bool scales;      // AC susceptance proportional to capacity
+  int line_off, node_off;
   int64_t eta_off;  // global capacity offset
   std::vector<double> eta_min, eta_max;
 };
@@ -170,10 +172,17 @@ struct gp_plan {
   // device data
   DevBuf<ScenDev> d_scen;
   DevBuf<NetDev> d_net;
+  DevBuf<int32_t> d_gen_perm, d_line_perm;
   DevBuf<int32_t> d_gen_node, d_line_from, d_line_to, d_batt_node, d_term_ptr, d_term, d_ang_ptr,
       d_ang;
   DevBuf<float> d_gen_cost, d_gen_emis, d_line_beta, d_sig_bal, d_rho_th, d_taps, d_avail, d_load,
-      d_eta;
+      d_eta, d_line_dbeta;
+  // capacity-dependent susceptance: host copies of the device values and
+  // what they are computed from
+  bool any_scaling = false;
+  std::vector<double> beta_base;       // per line (global order): input beta, 0 for HVDC links
+  std::vector<int32_t> lfrom, lto;     // per line: network-local endpoints
+  std::vector<float> beta_cur, rhoth_cur;
   DevBuf<float> d_x, d_x0, d_xhat;
   DevBuf<double> d_y0, d_yhat;
   DevBuf<float> d_dbar;
@@ -287,6 +296,11 @@ void validate_case(const gp_case_desc* cs) {
     for (int b = 0; b < n.n_batt; ++b)
       if (n.batt_node[b] < 0 || n.batt_node[b] >= n.n_nodes)
         fail(GP_EINVAL, "network %d battery %d: bad node", k, b);
+    if (n.beta_scales != 0 && n.beta_scales != 1) fail(GP_EINVAL, "network %d: beta_scales must be 0 or 1", k);
+    if (n.beta_scales)
+      for (int l = 0; l < n.n_lines - n.n_hvdc; ++l)
+        if (!(n.eta_min[n.n_gens + l] > 0))
+          fail(GP_EINVAL, "network %d line %d: a scaling susceptance needs eta_min > 0", k, l);
     const int Kn = n.n_gens + n.n_lines + n.n_batt;
     for (int j = 0; j < Kn; ++j)
       if (!(n.eta_min[j] >= 0) || !finite(n.eta_min[j]) || !finite(n.eta_max[j]) ||
@@ -333,8 +347,8 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   w.rho_b = w.wb + w.ws;
 
   std::vector<NetDev> nd;
-  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang;
-  std::vector<float> gen_cost, gen_emis, line_beta, sig_bal, rho_th;
+  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang, gen_perm, line_perm;
+  std::vector<float> gen_cost, gen_emis, line_beta, line_dbeta, sig_bal, rho_th;
   double qinf = cs->lambda_u;
   int64_t eta_off = 0;
   for (int k = 0; k < cs->n_networks; ++k) {
@@ -364,6 +378,22 @@ void build(gp_plan* p, const gp_case_desc* cs) {
       line_from.push_back(n.line_from[l]);
       line_to.push_back(n.line_to[l]);
       line_beta.push_back(l < d.Lac ? (float)n.line_beta[l] : 0.f);
+      // the susceptance at eta_min is line_beta itself, so the build's
+      // values hold until a solve moves the capacities
+      line_dbeta.push_back(n.beta_scales && l < d.Lac ? (float)(n.line_beta[l] / n.eta_min[d.G + l]) : 0.f);
+      p->beta_base.push_back(l < d.Lac ? n.line_beta[l] : 0.0);
+      p->lfrom.push_back(n.line_from[l]);
+      p->lto.push_back(n.line_to[l]);
+    }
+    {  // visiting orders of the variable sweep (stable: equal nodes keep their order)
+      std::vector<int32_t> o(d.G);
+      for (int g = 0; g < d.G; ++g) o[g] = g;
+      std::stable_sort(o.begin(), o.end(), [&](int32_t u, int32_t v) { return n.gen_node[u] < n.gen_node[v]; });
+      gen_perm.insert(gen_perm.end(), o.begin(), o.end());
+      o.resize(d.L);
+      for (int l = 0; l < d.L; ++l) o[l] = l;
+      std::stable_sort(o.begin(), o.end(), [&](int32_t u, int32_t v) { return n.line_from[u] < n.line_from[v]; });
+      line_perm.insert(line_perm.end(), o.begin(), o.end());
     }
     for (int b = 0; b < d.B; ++b) batt_node.push_back(n.batt_node[b]);
     // node -> terminals (balance rows) and node -> incident lines (angles)
@@ -401,6 +431,10 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     nh.G = d.G;
     nh.B = d.B;
     nh.Lac = d.Lac;
+    nh.scales = n.beta_scales != 0;
+    nh.line_off = d.line_off;
+    nh.node_off = d.node_off;
+    p->any_scaling = p->any_scaling || nh.scales;
     nh.eta_off = eta_off;
     const int Kn = d.G + d.L + d.B;
     nh.eta_min.assign(n.eta_min, n.eta_min + Kn);
@@ -494,11 +528,16 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->d_net.upload(nd, st);
   p->d_scen.upload(sd, st);
   p->d_gen_node.upload(gen_node, st);
+  p->d_gen_perm.upload(gen_perm, st);
+  p->d_line_perm.upload(line_perm, st);
   p->d_gen_cost.upload(gen_cost, st);
   p->d_gen_emis.upload(gen_emis, st);
   p->d_line_from.upload(line_from, st);
   p->d_line_to.upload(line_to, st);
   p->d_line_beta.upload(line_beta, st);
+  p->d_line_dbeta.upload(line_dbeta, st);
+  p->beta_cur = line_beta;
+  p->rhoth_cur = rho_th;
   p->d_batt_node.upload(batt_node, st);
   p->d_term_ptr.upload(term_ptr, st);
   p->d_term.upload(term, st);
@@ -569,11 +608,14 @@ Args make_args(gp_plan* p, int adjoint) {
   a.mode = adjoint;
   a.qgrab = p->qgrab;
   a.gen_node = p->d_gen_node.p;
+  a.gen_perm = p->d_gen_perm.p;
+  a.line_perm = p->d_line_perm.p;
   a.gen_cost = p->d_gen_cost.p;
   a.gen_emis = p->d_gen_emis.p;
   a.line_from = p->d_line_from.p;
   a.line_to = p->d_line_to.p;
   a.line_beta = p->d_line_beta.p;
+  a.line_dbeta = p->d_line_dbeta.p;
   a.batt_node = p->d_batt_node.p;
   a.term_ptr = p->d_term_ptr.p;
   a.term = p->d_term.p;
@@ -1181,15 +1223,42 @@ void check_eta(const gp_plan* p, const double* eta) {
   }
 }
 
+// Capacities to the device (FP32).  Where a network's susceptances scale with
+// line capacity, the lines' beta(eta) and the nodes' angle copy weights
+// (wth * sum of incident beta^2) are recomputed in FP64 from eta and stored
+// in FP32 (the step of the flow rows does not depend on beta).
+void set_eta(gp_plan* p, const double* eta) {
+  std::vector<float> ef(std::max<int64_t>(p->K, 1));
+  for (int64_t j = 0; j < p->K; ++j) ef[j] = (float)eta[j];
+  HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  if (p->any_scaling) {
+    for (const NetHost& n : p->nets) {
+      if (!n.scales) continue;
+      std::vector<double> b2(n.N, 0.0);
+      for (int l = 0; l < n.Lac; ++l) {
+        const int gl = n.line_off + l;
+        const float b = (float)(p->beta_base[gl] * eta[n.eta_off + n.G + l] / n.eta_min[n.G + l]);
+        p->beta_cur[gl] = b;
+        b2[p->lfrom[gl]] += (double)b * b;
+        b2[p->lto[gl]] += (double)b * b;
+      }
+      for (int v = 0; v < n.N; ++v) p->rhoth_cur[n.node_off + v] = (float)(p->w.wth * b2[v]);
+    }
+    HIPCHK(hipMemcpyAsync(p->d_line_beta.p, p->beta_cur.data(), p->beta_cur.size() * sizeof(float),
+                          hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(p->d_rho_th.p, p->rhoth_cur.data(), p->rhoth_cur.size() * sizeof(float),
+                          hipMemcpyHostToDevice, p->stream));
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));
+}
+
 int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, int32_t warm,
                double* cost_out, gp_solve_stats* stats_out) {
   std::vector<int> batch;
   check_batch(p, scen, nb, batch);
   check_eta(p, eta);
   if (warm != 0 && warm != 1) fail(GP_EINVAL, "warm_mode must be 0 or 1");
-  std::vector<float> ef(std::max<int64_t>(p->K, 1));
-  for (int64_t j = 0; j < p->K; ++j) ef[j] = (float)eta[j];
-  HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  set_eta(p, eta);
   build_tiles(p, batch);
   autotune(p, batch);
   std::vector<double> einf;
@@ -1255,7 +1324,7 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
   Args ag = a;
   ag.amask = p->d_mask.p;
   ag.stats = p->d_gpart.p;
-  HIPCHK(launch_grad(ag, p->d_goff.p, nb, ndev, 0, st));
+  HIPCHK(launch_grad(ag, p->d_goff.p, nb, ndev, 0, a.xhat, a.yhat, st));
   HIPCHK(hipMemcpyAsync(p->h_gpart.p, p->d_gpart.p, ndev * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   std::vector<double> g(ndev);
@@ -1285,7 +1354,7 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
     Args aa = make_args(p, 1);
     aa.omega = (float)omega;
     aa.stats = p->d_gpart.p;
-    HIPCHK(launch_grad(aa, p->d_goff.p, nb, ndev, 1, st));
+    HIPCHK(launch_grad(aa, p->d_goff.p, nb, ndev, 1, a.xhat, a.yhat, st));
     HIPCHK(hipMemcpyAsync(p->h_gpart.p, p->d_gpart.p, ndev * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int64_t i = 0; i < ndev; ++i) g[i] += p->h_gpart[i];
@@ -1564,10 +1633,7 @@ static void nn_prepare(gp_plan* p, const double* eta, const int32_t* scen, int32
   rows = nn_layout(p, batch, ro, T);
   if (eta) {
     check_eta(p, eta);
-    std::vector<float> ef(std::max<int64_t>(p->K, 1));
-    for (int64_t j = 0; j < p->K; ++j) ef[j] = (float)eta[j];
-    HIPCHK(hipMemcpyAsync(p->d_eta.p, ef.data(), p->K * sizeof(float), hipMemcpyHostToDevice, p->stream));
-    HIPCHK(hipStreamSynchronize(p->stream));
+    set_eta(p, eta);
   }
   build_tiles(p, batch);
   p->d_rowoff.upload(ro, p->stream);

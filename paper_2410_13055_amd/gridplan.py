@@ -45,7 +45,7 @@ class gp_network(C.Structure):
                 ("line_beta", C.POINTER(C.c_double)), ("gen_node", C.POINTER(C.c_int32)),
                 ("gen_cost", C.POINTER(C.c_double)), ("gen_emis", C.POINTER(C.c_double)),
                 ("batt_node", C.POINTER(C.c_int32)), ("eta_min", C.POINTER(C.c_double)),
-                ("eta_max", C.POINTER(C.c_double)), ("n_hvdc", C.c_int32)]
+                ("eta_max", C.POINTER(C.c_double)), ("n_hvdc", C.c_int32), ("beta_scales", C.c_int32)]
 
 
 class gp_scenario(C.Structure):
@@ -188,7 +188,8 @@ class _Descriptor:
                 _ptr(arrs["line_beta"], C.c_double), _ptr(arrs["gen_node"], C.c_int32),
                 _ptr(arrs["gen_cost"], C.c_double), _ptr(arrs["gen_emis"], C.c_double),
                 _ptr(arrs["batt_node"], C.c_int32), _ptr(arrs["eta_min"], C.c_double),
-                _ptr(arrs["eta_max"], C.c_double), int(getattr(n, "n_hvdc", 0)))
+                _ptr(arrs["eta_max"], C.c_double), int(getattr(n, "n_hvdc", 0)),
+                int(getattr(n, "beta_scales", False)))
         scs = (gp_scenario * len(case.scenarios))()
         for i, s in enumerate(case.scenarios):
             av = np.ascontiguousarray(s.avail, np.float32)

@@ -67,6 +67,9 @@ def _init(case, opts=None):
     (lambda c: c.networks[0].eta_min.__setitem__(-1, 0.0), "battery 1: capacity lower bound"),
     (lambda c: setattr(c.networks[0], "n_hvdc", c.networks[0].n_lines + 1), "bad counts"),
     (lambda c: setattr(c.networks[0], "n_hvdc", -1), "bad counts"),
+    (lambda c: setattr(c.networks[0], "beta_scales", 2), "beta_scales"),
+    (lambda c: (setattr(c.networks[0], "beta_scales", True), c.networks[0].eta_min.__setitem__(12, 0.0)),
+     "scaling susceptance needs eta_min > 0"),
 ])
 def test_plan_init_rejects_bad_case(mutate, needle):
     cs = cases.config0()
