@@ -103,8 +103,6 @@ struct Args {
   int32_t qgrab;       // work-queue form: tiles taken per counter update
   // network data
   const int32_t* gen_node;
-  const int32_t* gen_perm;  // variable sweep's visiting order: generators by node
-  const int32_t* line_perm; // ... and lines by their 'from' node (network-local indices)
   const float* gen_cost;
   const float* gen_emis;
   const int32_t* line_from;

@@ -456,33 +456,28 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
   double ey[4];
   switch (tl.cls & 0xff) {
     case VC_GEN: {
-      // generators are visited in node order (gen_perm), so the balance
-      // duals a block gathers come from few nodes
-      const int gq = i / T, t = i - gq * T;
-      const int g = a.gen_perm[nt.gen_off + gq];
-      const int ig = g * T + t;
+      const int g = i / T, t = i - g * T;
       const int n = a.gen_node[nt.gen_off + g];
-      const f4 hi = ld4(a.avail + sc.aoff + ig) * a.eta[nt.eta_off + g];
+      const f4 hi = ld4(a.avail + sc.aoff + i) * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
       ldy4(a, yb + (int64_t)n * TT + t, ey);
-      upd4(u, ig, ey, q, a.w.wb, zero, hi);
+      upd4(u, i, ey, q, a.w.wb, zero, hi);
       break;
     }
     case VC_LINE: {
-      const int lq = i / T, t = i - lq * T;
-      const int l = a.line_perm[nt.line_off + lq];  // lines in order of their 'from' node
-      const int il = l * T + t;
+      const int l = i / T, t = i - l * T;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-      double pto[4], pfr[4], mu[4] = {0.0, 0.0, 0.0, 0.0};
+      double pto[4], pfr[4], mu[4];
       ldy4(a, yb + (int64_t)to * TT + t, pto);
       ldy4(a, yb + (int64_t)fr * TT + t, pfr);
-      const bool ac = l < nt.Lac;  // an HVDC link has no flow-row copy
-      if (ac) ldy4(a, yf + il, mu);
+      // an HVDC link's flow-row slot holds zero, so the load needs no branch;
+      // only its weight drops the flow copy
+      ldy4(a, yf + i, mu);
 #pragma unroll
       for (int k = 0; k < 4; ++k) ey[k] = pto[k] - pfr[k] + mu[k];
       const float cap = a.eta[nt.eta_off + nt.G + l];
       const f4 hi = {cap, cap, cap, cap};
-      upd4(u, (int64_t)nt.G * TT + il, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -hi, hi);
+      upd4(u, (int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + (l < nt.Lac ? a.cwf[s] * a.w.wf : 0.f), -hi, hi);
       break;
     }
     case VC_NODE: {
@@ -560,25 +555,19 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
   const int64_t ys = yf + (int64_t)nt.L * TT;  // SOC rows
   switch (tl.cls) {
     case VC_GEN: {
-      const int gq = i / T, t = i - gq * T;
-      const int g = a.gen_perm[nt.gen_off + gq];
-      const int ig = g * T + t;
+      const int g = i / T, t = i - g * T;
       const int n = a.gen_node[nt.gen_off + g];
-      const float hi = a.avail[sc.aoff + ig] * a.eta[nt.eta_off + g];
+      const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
-      u(ig, ldy(a, yb + (int64_t)n * TT + t), q, a.w.wb, 0.f, hi);
+      u(i, ldy(a, yb + (int64_t)n * TT + t), q, a.w.wb, 0.f, hi);
       break;
     }
     case VC_LINE: {
-      const int lq = i / T, t = i - lq * T;
-      const int l = a.line_perm[nt.line_off + lq];
-      const int il = l * T + t;
+      const int l = i / T, t = i - l * T;
       const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
-      const bool ac = l < nt.Lac;
-      const double ey = ldy(a, yb + (int64_t)to * TT + t) - ldy(a, yb + (int64_t)fr * TT + t) +
-                        (ac ? ldy(a, yf + il) : 0.0);
+      const double ey = ldy(a, yb + (int64_t)to * TT + t) - ldy(a, yb + (int64_t)fr * TT + t) + ldy(a, yf + i);
       const float cap = a.eta[nt.eta_off + nt.G + l];
-      u((int64_t)nt.G * TT + il, ey, 0.f, 2.f * a.w.wb + (ac ? a.cwf[s] * a.w.wf : 0.f), -cap, cap);
+      u((int64_t)nt.G * TT + i, ey, 0.f, 2.f * a.w.wb + (l < nt.Lac ? a.cwf[s] * a.w.wf : 0.f), -cap, cap);
       break;
     }
     case VC_NODE: {

@@ -172,7 +172,6 @@ struct gp_plan {
   // device data
   DevBuf<ScenDev> d_scen;
   DevBuf<NetDev> d_net;
-  DevBuf<int32_t> d_gen_perm, d_line_perm;
   DevBuf<int32_t> d_gen_node, d_line_from, d_line_to, d_batt_node, d_term_ptr, d_term, d_ang_ptr,
       d_ang;
   DevBuf<float> d_gen_cost, d_gen_emis, d_line_beta, d_sig_bal, d_rho_th, d_taps, d_avail, d_load,
@@ -347,7 +346,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   w.rho_b = w.wb + w.ws;
 
   std::vector<NetDev> nd;
-  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang, gen_perm, line_perm;
+  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang;
   std::vector<float> gen_cost, gen_emis, line_beta, line_dbeta, sig_bal, rho_th;
   double qinf = cs->lambda_u;
   int64_t eta_off = 0;
@@ -384,16 +383,6 @@ void build(gp_plan* p, const gp_case_desc* cs) {
       p->beta_base.push_back(l < d.Lac ? n.line_beta[l] : 0.0);
       p->lfrom.push_back(n.line_from[l]);
       p->lto.push_back(n.line_to[l]);
-    }
-    {  // visiting orders of the variable sweep (stable: equal nodes keep their order)
-      std::vector<int32_t> o(d.G);
-      for (int g = 0; g < d.G; ++g) o[g] = g;
-      std::stable_sort(o.begin(), o.end(), [&](int32_t u, int32_t v) { return n.gen_node[u] < n.gen_node[v]; });
-      gen_perm.insert(gen_perm.end(), o.begin(), o.end());
-      o.resize(d.L);
-      for (int l = 0; l < d.L; ++l) o[l] = l;
-      std::stable_sort(o.begin(), o.end(), [&](int32_t u, int32_t v) { return n.line_from[u] < n.line_from[v]; });
-      line_perm.insert(line_perm.end(), o.begin(), o.end());
     }
     for (int b = 0; b < d.B; ++b) batt_node.push_back(n.batt_node[b]);
     // node -> terminals (balance rows) and node -> incident lines (angles)
@@ -528,8 +517,6 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->d_net.upload(nd, st);
   p->d_scen.upload(sd, st);
   p->d_gen_node.upload(gen_node, st);
-  p->d_gen_perm.upload(gen_perm, st);
-  p->d_line_perm.upload(line_perm, st);
   p->d_gen_cost.upload(gen_cost, st);
   p->d_gen_emis.upload(gen_emis, st);
   p->d_line_from.upload(line_from, st);
@@ -608,8 +595,6 @@ Args make_args(gp_plan* p, int adjoint) {
   a.mode = adjoint;
   a.qgrab = p->qgrab;
   a.gen_node = p->d_gen_node.p;
-  a.gen_perm = p->d_gen_perm.p;
-  a.line_perm = p->d_line_perm.p;
   a.gen_cost = p->d_gen_cost.p;
   a.gen_emis = p->d_gen_emis.p;
   a.line_from = p->d_line_from.p;
