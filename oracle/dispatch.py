@@ -19,6 +19,10 @@ variables (canonical order, each block [device][hour])
     dis [B,T]  battery discharge            0 <= dis <= eta_k
     soc [B,T]  battery state of charge      0 <= soc <= H * eta_k
     u   [N,T]  unserved load                u >= 0
+    s   [R,T]  ramp of a ramp-limited generator g_r between hours t-1 and t,
+               -rho_g eta_g <= s <= rho_g eta_g  (rho_g: the share of its
+               capacity a unit can move in an hour; units without a limit
+               have no ramp variables)
 
 equalities (canonical order; duals y = [pi | mu | nu])
     balance [N,T]: sum_{g at n} p + sum_{k at n} (dis - ch) + u
@@ -31,6 +35,7 @@ equalities (canonical order; duals y = [pi | mu | nu])
                    an expanded line is parallel circuits of the same kind)
                    beta_l = line_beta_l * eta_l / eta_min_l.
     soc     [B,T]: soc[t] - soc[t-1] - eff * ch[t] + dis[t] = 0, cyclic in t
+    ramp    [R,T]: p[g_r,t] - p[g_r,t-1] - s[r,t] = 0, cyclic in t
 
 objective
     c(x) = sum c_g p + lambda_u sum u + (r/2) ||x||^2
@@ -93,9 +98,9 @@ class QP:
         return self.E.shape[0]
 
 
-def block_slices(G, L, N, B, T):
+def block_slices(G, L, N, B, T, R=0):
     """Canonical variable blocks (the ordering both sides agree on)."""
-    sizes = [("p", G), ("f", L), ("th", N), ("ch", B), ("dis", B), ("soc", B), ("u", N)]
+    sizes = [("p", G), ("f", L), ("th", N), ("ch", B), ("dis", B), ("soc", B), ("u", N), ("s", R)]
     out, o = {}, 0
     for name, c in sizes:
         out[name] = slice(o, o + c * T)
@@ -104,9 +109,9 @@ def block_slices(G, L, N, B, T):
     return out
 
 
-def row_slices(N, L, B, T):
+def row_slices(N, L, B, T, R=0):
     out, o = {}, 0
-    for name, c in [("bal", N), ("flow", L), ("soc", B)]:
+    for name, c in [("bal", N), ("flow", L), ("soc", B), ("ramp", R)]:
         out[name] = slice(o, o + c * T)
         o += c * T
     out["m"] = o
@@ -120,11 +125,14 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
     net = case.networks[sc.network]
     G, L, N, B, T = net.n_gens, net.n_lines, net.n_nodes, net.n_batt, sc.T
     Lac = L - int(getattr(net, "n_hvdc", 0))
+    ramp = getattr(net, "gen_ramp", None)
+    rg = np.zeros(0, np.int64) if ramp is None else np.where(np.asarray(ramp) > 0)[0]
+    R = rg.shape[0]
     K = net.K
     eta_net = np.asarray(eta_net, dtype=np.float64)
     assert eta_net.shape == (K,)
-    vs = block_slices(G, L, N, B, T)
-    rs = row_slices(N, Lac, B, T)
+    vs = block_slices(G, L, N, B, T, R)
+    rs = row_slices(N, Lac, B, T, R)
     n, m = vs["n"], rs["m"]
     t = np.arange(T)
 
@@ -167,12 +175,18 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
     put(ridx("soc", kb), prev, -1.0)
     put(ridx("soc", kb), vidx("ch", kb), -case.eff)
     put(ridx("soc", kb), vidx("dis", kb), 1.0)
+    # ramp rows: p[g, t] - p[g, t-1] - s[r, t] = 0 (cyclic)
+    if R:
+        rr = np.arange(R)
+        put(ridx("ramp", rr), vidx("p", rg), 1.0)
+        put(ridx("ramp", rr), vs["p"].start + rg[:, None] * T + ((t - 1) % T)[None, :], -1.0)
+        put(ridx("ramp", rr), vidx("s", rr), -1.0)
 
     E = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(m, n))
     E.sum_duplicates()
-    if T == 1 and B > 0:
-        # soc[t] - soc[t-1] cancels when T == 1; drop explicit zeros
+    if T == 1 and (B > 0 or R > 0):
+        # soc[t] - soc[t-1] and p[t] - p[t-1] cancel when T == 1; drop explicit zeros
         E.eliminate_zeros()
 
     e = np.zeros(m)
@@ -214,9 +228,18 @@ def assemble(case, s: int, eta_net: np.ndarray) -> QP:
         hi_idx[vs[blk]] = np.repeat(G + L + np.arange(B), T)
         hi_coef[vs[blk]] = mult
 
+    if R:
+        rho = np.asarray(ramp, np.float64)[rg]
+        hi[vs["s"]] = np.repeat(rho * eg[rg], T)
+        lo[vs["s"]] = -np.repeat(rho * eg[rg], T)
+        hi_idx[vs["s"]] = np.repeat(rg, T)
+        lo_idx[vs["s"]] = np.repeat(rg, T)
+        hi_coef[vs["s"]] = np.repeat(rho, T)
+        lo_coef[vs["s"]] = -np.repeat(rho, T)
+
     return QP(E=E, e=e, q=q, lo=lo, hi=hi, r=float(case.r), hi_idx=hi_idx, hi_coef=hi_coef,
               lo_idx=lo_idx, lo_coef=lo_coef, emis=emis, fuel=fuel,
-              dims=dict(G=G, L=L, Lac=Lac, N=N, B=B, T=T, vs=vs, rs=rs,
+              dims=dict(G=G, L=L, Lac=Lac, N=N, B=B, T=T, R=R, ramp_gen=rg, vs=vs, rs=rs,
                         line_from=np.asarray(net.line_from), line_to=np.asarray(net.line_to)), K=K,
               line_dbeta=dbeta if dbeta.any() else None)
 

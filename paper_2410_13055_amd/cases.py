@@ -59,6 +59,7 @@ class Network:
     gamma: np.ndarray       # float64 [K] $/MW-yr investment cost
     n_hvdc: int = 0         # the last n_hvdc lines are HVDC links (their beta is unused)
     beta_scales: bool = False  # AC susceptance beta_l * eta_l / eta_min_l (parallel circuits)
+    gen_ramp: Optional[np.ndarray] = None  # float64 [G]: share of capacity a unit can move per hour (0: no limit)
 
     @property
     def n_lines(self) -> int:
@@ -401,14 +402,20 @@ def config2(seed=None, S=64) -> Case:
     return Case(name="uneven64", networks=nets, scenarios=scens)
 
 
-def small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, omega=0.0, n_hvdc=0, beta_scales=False) -> Case:
+def small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, omega=0.0, n_hvdc=0, beta_scales=False,
+              gas_ramp=0.0) -> Case:
     """A small geometric case (for quick parity tests): several tiles of
     work per class and a ragged tail at any block size.  With n_hvdc > 0
     that many HVDC links are added after the AC lines; with beta_scales the
-    AC susceptances scale with line capacity."""
-    cs = _uniform_case(f"geo{n_nodes}" + (f"_hvdc{n_hvdc}" if n_hvdc else "") + ("_scaled" if beta_scales else ""),
+    AC susceptances scale with line capacity; with gas_ramp > 0 every gas
+    unit can move at most that share of its capacity per hour."""
+    cs = _uniform_case(f"geo{n_nodes}" + (f"_hvdc{n_hvdc}" if n_hvdc else "") + ("_scaled" if beta_scales else "")
+                       + (f"_ramp{gas_ramp:g}" if gas_ramp else ""),
                        100, n_nodes, G, B, T, S, "geo", omega=omega, seed=seed, n_hvdc=n_hvdc)
-    cs.networks[0].beta_scales = bool(beta_scales)
+    net = cs.networks[0]
+    net.beta_scales = bool(beta_scales)
+    if gas_ramp:
+        net.gen_ramp = _f32(np.where(net.gen_kind == GAS, gas_ramp, 0.0))
     return cs
 
 
