@@ -26,13 +26,16 @@
  *            and is otherwise free within its capacity; beta_l may scale
  *            with eta_l, see gp_network.beta_scales)
  *   soc:     soc[t] - soc[t-1] - eff ch[t] + dis[t] = 0, cyclic (dual: nu)
+ *   ramp:    p[g,t] - p[g,t-1] - s[r,t] = 0, cyclic, for the R units with a
+ *            ramp limit, s[r,t] in [-rho_g eta_g, rho_g eta_g]  (dual: kappa)
  *   c_s(x) = sum cost_g p + lambda_u sum u + (r/2) ||x||^2
  *   h_s(x) = c_s(x) + omega * sum emis_g p   (emissions-aware planning)
  *
  * Canonical per-scenario vector orders (used by the accessors):
- *   x = [p (G*T) | f (L*T) | th (N*T) | ch (B*T) | dis (B*T) | soc (B*T) | u (N*T)]
- *   y = [pi (N*T) | mu (L_ac*T) | nu (B*T)], every block [device][hour],
- *   with L_ac = n_lines - n_hvdc (the AC lines come first).
+ *   x = [p (G*T) | f (L*T) | th (N*T) | ch (B*T) | dis (B*T) | soc (B*T) | u (N*T) | s (R*T)]
+ *   y = [pi (N*T) | mu (L_ac*T) | nu (B*T) | kappa (R*T)], every block
+ *   [device][hour], with L_ac = n_lines - n_hvdc (the AC lines come first)
+ *   and the ramp blocks in generator order.
  * Capacity vector per network: eta = [generators | lines | batteries];
  * across networks the vectors are concatenated in network order (K total).
  *
@@ -88,6 +91,10 @@ typedef struct {
                                 eta_min_l (an expanded corridor of parallel
                                 circuits), so AC lines need eta_min > 0; the
                                 gradient then includes the matrix terms */
+  const double* gen_ramp;    /* [n_gens] or NULL: share of its capacity a unit
+                                can move between consecutive hours (>= 0, 0 =
+                                no limit): rows p[g,t] - p[g,t-1] - s[g,t] = 0
+                                (cyclic) with |s| <= gen_ramp[g] * eta_g */
 } gp_network;
 
 /* One operating scenario (Section 2.1: each scenario s has its own cost and

@@ -14,7 +14,7 @@ enum Stat {
   ST_DUAL_MAX = 1,  // max |(E'y - q - r x)| over free entries (max-reduced)
   ST_XMAX = 2,      // max |x|                           (max-reduced)
   ST_RESF_MAX = 3,  // max |E x - e| over flow rows      (max-reduced)
-  ST_RESS_MAX = 4,  // max |E x - e| over SOC rows       (max-reduced)
+  ST_RESS_MAX = 4,  // max |E x - e| over SOC and ramp rows (max-reduced)
   ST_P = 5,         // (r/2)||x||^2 + q'x
   ST_D = 6,         // dual function value
   ST_DX2 = 7,       // sum rho_i (xhat - x0)^2
@@ -29,9 +29,9 @@ enum Stat {
 constexpr int kMaxStats = 5;  // slots [0, kMaxStats) are maxima, the rest sums
 
 // work classes of the primal (variable) sweep
-enum VarClass { VC_GEN = 0, VC_LINE = 1, VC_NODE = 2, VC_BATT = 3 };
+enum VarClass { VC_GEN = 0, VC_LINE = 1, VC_NODE = 2, VC_BATT = 3, VC_RAMP = 4 };
 // work classes of the dual (row) sweep
-enum RowClass { RC_BAL = 0, RC_FLOW = 1, RC_SOC = 2 };
+enum RowClass { RC_BAL = 0, RC_FLOW = 1, RC_SOC = 2, RC_RAMP = 3 };
 // work-queue counters: one per XCD, kQueueStride u64 words apart; a sweep
 // uses kQueueWords words (dual sweep first, then the primal sweep)
 constexpr int kXcd = 8;
@@ -73,6 +73,9 @@ struct NetDev {
   int32_t Lac;       // AC lines [0, Lac) have a flow row; lines [Lac, L) are
                      // HVDC links: their flow-row slots stay zero, and their
                      // susceptance is stored as 0 so no angle sees them
+  int32_t R;         // ramp-limited generators (ramp variables s [R][T] after
+                     // u in x, ramp rows [R][T] after the SOC rows in y)
+  int32_t ramp_off;  // into ramp_gen / ramp_rho
 };
 
 // terminal codes of the nodal-balance CSR: (index << 2) | type
@@ -84,6 +87,9 @@ struct Weights {
   float wf;     // flow-row copy weight of the line flow
   float wth;    // flow-row copy weight of an angle, per beta^2
   float ws;     // SOC-chain copy weight
+  float wr;     // ramp-row copy weight of a generator output (two per output)
+  float wsr;    // ramp-row copy weight of a ramp variable
+  float sig_ramp;  // 1 / (2/wr + 1/wsr): the ramp rows' dual step
   float sig_flow;  // 1 / (1/wf + 2/wth)
   float rho_f;  // 2 wb + wf
   float rho_b;  // wb + ws  (ch, dis)
@@ -109,6 +115,9 @@ struct Args {
   const int32_t* line_to;
   const float* line_beta;   // susceptance at the current capacities (0 for HVDC links)
   const float* line_dbeta;  // d beta_l / d eta_l (0 unless the line's susceptance scales)
+  const int32_t* gen_ramp;  // per generator: its ramp index (network-local) or -1
+  const int32_t* ramp_gen;  // per ramp index: the generator (network-local)
+  const float* ramp_rho;    // per ramp index: share of capacity per hour
   const int32_t* batt_node;
   const int32_t* term_ptr;
   const int32_t* term;

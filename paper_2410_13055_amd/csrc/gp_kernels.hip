@@ -93,6 +93,15 @@ __device__ __forceinline__ float soc_residual(const NetDev& nt, const float* xs,
   return psoc[t] - psoc[tp] - eff * pch[t] + pdis[t];
 }
 
+// residual of ramp row (r, t): p[g, t] - p[g, t-1] - s[r, t] (cyclic)
+__device__ __forceinline__ float ramp_residual(const Args& a, const NetDev& nt, const float* xs, int T, int rk,
+                                               int t) {
+  const int64_t TT = T;
+  const int g = a.ramp_gen[nt.ramp_off + rk];
+  const float* pg = xs + (int64_t)g * TT;
+  return pg[t] - pg[t == 0 ? T - 1 : t - 1] - xs[(int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + (int64_t)rk * TT + t];
+}
+
 // lamp = lambda_{k-1} = k / (k + 1) (0 right after a restart, where the
 // stored offset is zero anyway)
 __device__ __forceinline__ void dual_update(const Args& a, int64_t row, double step, double lamp,
@@ -195,6 +204,18 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
 #pragma unroll
     for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
     dual_update4(a, sc.yoff + i, step, lam, check);
+  } else if ((tl.cls & 0xff) == RC_RAMP) {
+    // p[g, t] - p[g, t-1] - s[r, t], cyclic in t
+    const int rk = i / T, t = i - rk * T;
+    const int g = a.ramp_gen[nt.ramp_off + rk];
+    const float* pg = xs + (int64_t)g * TT;
+    const f4 pv = ld4(pg + t);
+    const f4 pp = {pg[t == 0 ? T - 1 : t - 1], pv[0], pv[1], pv[2]};
+    const f4 res = pv - pp - ld4(xs + (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i);
+    const double f = c * (double)a.w.sig_ramp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
+    dual_update4(a, sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i, step, lam, check);
   } else {  // RC_FLOW
     const int l = i / T, t = i - l * T;
     const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
@@ -354,6 +375,11 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
     const float load = a.mode ? 0.f : a.load[sc.doff + i];
     const float res = bal_residual(a, nt, xs, T, n, t, load);
     dual_update(a, sc.yoff + i, c * (double)a.sig_bal[nt.node_off + n] * (double)res, lam, check);
+  } else if (tl.cls == RC_RAMP) {
+    const int rk = i / T, t = i - rk * T;
+    const float res = ramp_residual(a, nt, xs, T, rk, t);
+    dual_update(a, sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i, c * (double)a.w.sig_ramp * (double)res, lam,
+                check);
   } else {  // RC_FLOW
     const int l = i / T, t = i - l * T;
     const float res = flow_residual(a, nt, xs, T, l, t);
@@ -461,7 +487,29 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
       const f4 hi = ld4(a.avail + sc.aoff + i) * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
       ldy4(a, yb + (int64_t)n * TT + t, ey);
-      upd4(u, i, ey, q, a.w.wb, zero, hi);
+      float rho = a.w.wb;
+      const int rk = a.gen_ramp[nt.gen_off + g];
+      if (rk >= 0) {  // copies in ramp rows t (+1) and t + 1 (-1)
+        const int64_t yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
+        double nu[4];
+        ldy4(a, yr + t, nu);
+        const double nu_next = ldy(a, yr + ((t + 4 == T) ? 0 : t + 4));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ey[k] += nu[k] - (k < 3 ? nu[k + 1] : nu_next);
+        rho += 2.f * a.w.wr;
+      }
+      upd4(u, i, ey, q, rho, zero, hi);
+      break;
+    }
+    case VC_RAMP: {
+      const int rk = i / T;
+      const float cap = a.ramp_rho[nt.ramp_off + rk] * a.eta[nt.eta_off + a.ramp_gen[nt.ramp_off + rk]];
+      const f4 hi = {cap, cap, cap, cap};
+      double nu[4];
+      ldy4(a, yb + (int64_t)(nt.N + nt.L + nt.B) * TT + i, nu);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ey[k] = -nu[k];
+      upd4(u, (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i, ey, 0.f, a.w.wsr, -hi, hi);
       break;
     }
     case VC_LINE: {
@@ -559,7 +607,22 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
       const int n = a.gen_node[nt.gen_off + g];
       const float hi = a.avail[sc.aoff + i] * a.eta[nt.eta_off + g];
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
-      u(i, ldy(a, yb + (int64_t)n * TT + t), q, a.w.wb, 0.f, hi);
+      double ey = ldy(a, yb + (int64_t)n * TT + t);
+      float rho = a.w.wb;
+      const int rk = a.gen_ramp[nt.gen_off + g];
+      if (rk >= 0) {
+        const int64_t yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
+        ey += ldy(a, yr + t) - ldy(a, yr + ((t + 1 == T) ? 0 : t + 1));
+        rho += 2.f * a.w.wr;
+      }
+      u(i, ey, q, rho, 0.f, hi);
+      break;
+    }
+    case VC_RAMP: {
+      const int rk = i / T;
+      const float cap = a.ramp_rho[nt.ramp_off + rk] * a.eta[nt.eta_off + a.ramp_gen[nt.ramp_off + rk]];
+      u((int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i, -ldy(a, yb + (int64_t)(nt.N + nt.L + nt.B) * TT + i),
+        0.f, a.w.wsr, -cap, cap);
       break;
     }
     case VC_LINE: {
@@ -743,6 +806,12 @@ __global__ __launch_bounds__(BS) void k_check_rows(Args a) {
         den = 1.0 / a.sig_bal[nt.node_off + n];
         row = sc.yoff + i;
         v[ST_D] += (double)load * (double)a.yhat[row];
+      } else if (tl.cls == RC_RAMP) {
+        const int rk = i / T, t = i - rk * T;
+        res = ramp_residual(a, nt, xs, T, rk, t);
+        den = 1.0 / (double)a.w.sig_ramp;
+        row = sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i;
+        slot = ST_RESS_MAX;
       } else {
         const int l = i / T, t = i - l * T;
         res = flow_residual(a, nt, xs, T, l, t);
@@ -823,9 +892,26 @@ __global__ __launch_bounds__(BS) void k_check_vars(Args a) {
         const double cost = a.gen_cost[nt.gen_off + g], em = a.gen_emis[nt.gen_off + g];
         const double q = a.mode ? (double)a.omega * em : cost;
         const double xv = xh[i];
-        var_stats(v, xv, x0[i], yb[(int64_t)n * TT + t], q, r, lo, hi, a.w.wb);
+        double ey = yb[(int64_t)n * TT + t];
+        double rho = a.w.wb;
+        const int rk = a.gen_ramp[nt.gen_off + g];
+        if (rk >= 0) {
+          const double* yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
+          ey += yr[t] - yr[(t + 1 == T) ? 0 : t + 1];
+          rho += 2.0 * a.w.wr;
+        }
+        var_stats(v, xv, x0[i], ey, q, r, lo, hi, rho);
         v[ST_EMIS] += em * xv;
         v[ST_FUEL] += cost * xv;
+        break;
+      }
+      case VC_RAMP: {
+        const int rk = i / T;
+        const double cap = (double)(a.ramp_rho[nt.ramp_off + rk] * a.eta[nt.eta_off + a.ramp_gen[nt.ramp_off + rk]]);
+        const int64_t idx = (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i;
+        double lo = -cap, hi = cap;
+        bnd(idx, lo, hi);
+        var_stats(v, xh[idx], x0[idx], -yb[(int64_t)(nt.N + nt.L + nt.B) * TT + i], 0.0, r, lo, hi, a.w.wsr);
         break;
       }
       case VC_LINE: {
@@ -948,6 +1034,7 @@ __global__ __launch_bounds__(BS) void k_reset(Args a, int mode) {
     switch (tl.cls) {
       case VC_GEN: idx[0] = i; break;
       case VC_LINE: idx[0] = (int64_t)nt.G * TT + i; break;
+      case VC_RAMP: idx[0] = (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i; break;
       case VC_NODE:
         idx[0] = (int64_t)(nt.G + nt.L) * TT + i;
         idx[1] = (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i;
@@ -984,7 +1071,8 @@ __global__ __launch_bounds__(BS) void k_reset(Args a, int mode) {
     step = BS;
     n = T;
   } else {
-    r0 = sc.yoff + (tl.cls == RC_BAL ? 0 : (int64_t)nt.N * TT) + tl.start;
+    r0 = sc.yoff + (tl.cls == RC_BAL ? 0 : tl.cls == RC_FLOW ? (int64_t)nt.N * TT : (int64_t)(nt.N + nt.L + nt.B) * TT) +
+         tl.start;
     first = threadIdx.x;
     step = BS;
     n = tl.count;
@@ -1054,11 +1142,27 @@ __global__ __launch_bounds__(BS) void k_grad(Args a, const int64_t* goff, int nb
     const int g = dev;
     const int n = a.gen_node[nt.gen_off + g];
     const double q = mode_adj ? (double)a.omega * a.gen_emis[nt.gen_off + g] : (double)a.gen_cost[nt.gen_off + g];
+    // the ramp rows move E'y of a held output too
+    const int rk = a.gen_ramp[nt.gen_off + g];
+    const double* yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)(rk < 0 ? 0 : rk) * TT;
     for (int t = lane; t < T; t += W) {
       const int64_t idx = (int64_t)g * TT + t;
       if (am[idx] & 2) {
-        const double z = (double)yb[(int64_t)n * TT + t] - q - r * (double)xh[idx];
+        double z = (double)yb[(int64_t)n * TT + t] - q - r * (double)xh[idx];
+        if (rk >= 0) z += yr[t] - yr[(t + 1 == T) ? 0 : t + 1];
         acc += (double)a.avail[sc.aoff + idx] * (-z);
+      }
+    }
+    // ramp variables at their bounds +-rho eta_g (coefficient +-rho)
+    if (rk >= 0) {
+      const double rho = a.ramp_rho[nt.ramp_off + rk];
+      const int64_t sb = (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + (int64_t)rk * TT;
+      for (int t = lane; t < T; t += W) {
+        const uint8_t m = am[sb + t];
+        if (m) {
+          const double z = -yr[t] - r * (double)xh[sb + t];
+          acc += rho * ((m & 2) ? -z : z);
+        }
       }
     }
   } else if (dev < nt.G + nt.L) {
@@ -1149,7 +1253,12 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
         mk(i, hi);
       } else {  // zero capacity: upper side when more capacity would be used
         const int n = a.gen_node[nt.gen_off + g];
-        const double z = yb[(int64_t)n * TT + t] - (double)a.gen_cost[nt.gen_off + g] - (double)a.r * (double)xh[i];
+        double z = yb[(int64_t)n * TT + t] - (double)a.gen_cost[nt.gen_off + g] - (double)a.r * (double)xh[i];
+        const int rk = a.gen_ramp[nt.gen_off + g];
+        if (rk >= 0) {
+          const double* yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
+          z += yr[t] - yr[(t + 1 == T) ? 0 : t + 1];
+        }
         m[i] = z > 0.0 ? 2 : 1;
       }
       break;
@@ -1167,6 +1276,22 @@ __global__ __launch_bounds__(BS) void k_mask(Args a, uint8_t* mask) {
         const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
         const double mu = l < nt.Lac ? yb[(int64_t)nt.N * TT + (int64_t)l * TT + t] : 0.0;
         const double z = yb[(int64_t)to * TT + t] - yb[(int64_t)fr * TT + t] + mu - (double)a.r * (double)v;
+        b = z > 0.0 ? 2 : 1;
+      }
+      m[idx] = b;
+      break;
+    }
+    case VC_RAMP: {
+      const int rk = i / T;
+      const float cap = a.ramp_rho[nt.ramp_off + rk] * a.eta[nt.eta_off + a.ramp_gen[nt.ramp_off + rk]];
+      const int64_t idx = (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i;
+      const float v = xh[idx];
+      uint8_t b = 0;
+      if (cap > 0.f) {
+        if (v >= cap) b = 2;
+        else if (v <= -cap) b = 1;
+      } else {  // zero capacity: the side the ramp would take
+        const double z = -yb[(int64_t)(nt.N + nt.L + nt.B) * TT + i] - (double)a.r * (double)v;
         b = z > 0.0 ? 2 : 1;
       }
       m[idx] = b;
@@ -1445,7 +1570,8 @@ __global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, con
       // at the predicted prices is exact for uncongested lines but wrong for
       // congested ones (their bound multiplier takes the price difference),
       // and the wrong ones leave a large angle residual; zero measured faster.
-      yh[(int64_t)nt.N * TT + i] = 0.0;
+      // Ramp duals start at zero too.
+      yh[(tl.cls == RC_RAMP ? (int64_t)(nt.N + nt.L + nt.B) * TT : (int64_t)nt.N * TT) + i] = 0.0;
     }
     return;
   }
@@ -1469,6 +1595,9 @@ __global__ __launch_bounds__(BS) void k_start(Args a, const int32_t* rowoff, con
           clampf(b * (pred_angle(P, r0 + fr, T, t) - pred_angle(P, r0 + to, T, t)), -cap, cap);
       break;
     }
+    case VC_RAMP:
+      xh[(int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i] = 0.f;
+      break;
     case VC_NODE: {
       const int n = i / T, t = i - n * T;
       xh[(int64_t)(nt.G + nt.L) * TT + i] = pred_angle(P, r0 + n, T, t);

@@ -116,6 +116,7 @@ bool finite(double v) { return std::isfinite(v); }
 
 struct NetHost {
   int N, L, G, B;
+  int R;            // ramp-limited generators
   int Lac;          // AC lines (the rest are HVDC links)
   bool scales;      // AC susceptance proportional to capacity
   int line_off, node_off;
@@ -172,6 +173,8 @@ struct gp_plan {
   // device data
   DevBuf<ScenDev> d_scen;
   DevBuf<NetDev> d_net;
+  DevBuf<int32_t> d_gen_ramp, d_ramp_gen;
+  DevBuf<float> d_ramp_rho;
   DevBuf<int32_t> d_gen_node, d_line_from, d_line_to, d_batt_node, d_term_ptr, d_term, d_ang_ptr,
       d_ang;
   DevBuf<float> d_gen_cost, d_gen_emis, d_line_beta, d_sig_bal, d_rho_th, d_taps, d_avail, d_load,
@@ -296,6 +299,10 @@ void validate_case(const gp_case_desc* cs) {
       if (n.batt_node[b] < 0 || n.batt_node[b] >= n.n_nodes)
         fail(GP_EINVAL, "network %d battery %d: bad node", k, b);
     if (n.beta_scales != 0 && n.beta_scales != 1) fail(GP_EINVAL, "network %d: beta_scales must be 0 or 1", k);
+    if (n.gen_ramp)
+      for (int g = 0; g < n.n_gens; ++g)
+        if (!(n.gen_ramp[g] >= 0) || !finite(n.gen_ramp[g]))
+          fail(GP_EINVAL, "network %d generator %d: ramp limit must be finite and >= 0", k, g);
     if (n.beta_scales)
       for (int l = 0; l < n.n_lines - n.n_hvdc; ++l)
         if (!(n.eta_min[n.n_gens + l] > 0))
@@ -341,12 +348,16 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   w.wf = 1.f;    // flow-row copy of the line flow
   w.wth = 0.1f;  // flow-row copy of an angle, per beta^2
   w.ws = 1.f;    // SOC-chain copies
+  w.wr = 1.f;    // ramp-row copies of a generator output (rows t and t + 1)
+  w.wsr = 1.f;   // ramp-row copy of a ramp variable
+  w.sig_ramp = 1.f / (2.f / w.wr + 1.f / w.wsr);
   w.sig_flow = 1.f / (1.f / w.wf + 2.f / w.wth);
   w.rho_f = 2.f * w.wb + w.wf;
   w.rho_b = w.wb + w.ws;
 
   std::vector<NetDev> nd;
-  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang;
+  std::vector<int32_t> gen_node, line_from, line_to, batt_node, term_ptr, term, ang_ptr, ang, gen_ramp, ramp_gen;
+  std::vector<float> ramp_rho;
   std::vector<float> gen_cost, gen_emis, line_beta, line_dbeta, sig_bal, rho_th;
   double qinf = cs->lambda_u;
   int64_t eta_off = 0;
@@ -365,6 +376,17 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     d.aptr_off = (int32_t)ang_ptr.size();
     d.eta_off = (int32_t)eta_off;
     d.Lac = n.n_lines - n.n_hvdc;
+    d.ramp_off = (int32_t)ramp_gen.size();
+    for (int g = 0; g < d.G; ++g) {
+      if (n.gen_ramp && n.gen_ramp[g] > 0) {
+        gen_ramp.push_back((int32_t)(ramp_gen.size() - d.ramp_off));
+        ramp_gen.push_back(g);
+        ramp_rho.push_back((float)n.gen_ramp[g]);
+      } else {
+        gen_ramp.push_back(-1);
+      }
+    }
+    d.R = (int32_t)ramp_gen.size() - d.ramp_off;
     for (int g = 0; g < d.G; ++g) {
       gen_node.push_back(n.gen_node[g]);
       gen_cost.push_back((float)n.gen_cost[g]);
@@ -420,6 +442,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     nh.G = d.G;
     nh.B = d.B;
     nh.Lac = d.Lac;
+    nh.R = d.R;
     nh.scales = n.beta_scales != 0;
     nh.line_off = d.line_off;
     nh.node_off = d.node_off;
@@ -453,8 +476,8 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     d.yoff = yoff;
     d.aoff = (int64_t)avail.size();
     d.doff = (int64_t)load.size();
-    const int64_t nx = (int64_t)(n.G + n.L + 2 * n.N + 3 * n.B) * sc.T;
-    const int64_t ny = (int64_t)(n.N + n.L + n.B) * sc.T;
+    const int64_t nx = (int64_t)(n.G + n.L + 2 * n.N + 3 * n.B + n.R) * sc.T;
+    const int64_t ny = (int64_t)(n.N + n.L + n.B + n.R) * sc.T;
     avail.insert(avail.end(), sc.avail, sc.avail + (int64_t)n.G * sc.T);
     load.insert(load.end(), sc.load, sc.load + (int64_t)n.N * sc.T);
     double einf = 0.0, e2 = 0.0, q2 = 0.0;
@@ -505,7 +528,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
     sh.yoff = yoff;
     sh.nx = nx;
     sh.ny = ny;
-    sh.ny_out = (int64_t)(n.N + n.Lac + n.B) * sc.T;
+    sh.ny_out = (int64_t)(n.N + n.Lac + n.B + n.R) * sc.T;
     p->scen.push_back(sh);
     p->max_T = std::max(p->max_T, sc.T);
     xoff += (nx + 3) / 4 * 4;
@@ -517,6 +540,9 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->d_net.upload(nd, st);
   p->d_scen.upload(sd, st);
   p->d_gen_node.upload(gen_node, st);
+  p->d_gen_ramp.upload(gen_ramp, st);
+  p->d_ramp_gen.upload(ramp_gen, st);
+  p->d_ramp_rho.upload(ramp_rho, st);
   p->d_gen_cost.upload(gen_cost, st);
   p->d_gen_emis.upload(gen_emis, st);
   p->d_line_from.upload(line_from, st);
@@ -595,6 +621,9 @@ Args make_args(gp_plan* p, int adjoint) {
   a.mode = adjoint;
   a.qgrab = p->qgrab;
   a.gen_node = p->d_gen_node.p;
+  a.gen_ramp = p->d_gen_ramp.p;
+  a.ramp_gen = p->d_ramp_gen.p;
+  a.ramp_rho = p->d_ramp_rho.p;
   a.gen_cost = p->d_gen_cost.p;
   a.gen_emis = p->d_gen_emis.p;
   a.line_from = p->d_line_from.p;
@@ -679,6 +708,8 @@ void build_sweep_tiles(gp_plan* p, const std::vector<int>& subset) {
     adds(svt, VC_BATT, (int64_t)n.B * T);
     adds(srt, RC_BAL, (int64_t)n.N * T);
     adds(srt, RC_FLOW, (int64_t)n.Lac * T);  // AC lines only
+    adds(svt, VC_RAMP, (int64_t)n.R * T);
+    adds(srt, RC_RAMP, (int64_t)n.R * T);
     // battery chains: T/4 threads per chain, as many chains per block as fit
     const int cpb = v4 ? bs / (T / 4) : 0;
     if (cpb > 0)
@@ -724,6 +755,8 @@ void build_tiles(gp_plan* p, const std::vector<int>& batch, bool force = false) 
     add(vt, VC_BATT, (int64_t)n.B * T);
     add(rt, RC_BAL, (int64_t)n.N * T);
     add(rt, RC_FLOW, (int64_t)n.Lac * T);
+    add(vt, VC_RAMP, (int64_t)n.R * T);
+    add(rt, RC_RAMP, (int64_t)n.R * T);
     for (int k = 0; k < n.B; ++k) rt.push_back(Tile{s, RC_SOC, k, 1});
     ranges.push_back(v0);
     ranges.push_back((int)vt.size());
@@ -1489,8 +1522,8 @@ int dispatch_get_solution(gp_plan* p, int32_t s, float* x_out, double* y_out, in
     if ((x_out || y_out) && !p->has_solution[s]) fail(GP_ESTATE, "scenario %d has no solution yet", s);
     if (x_out)
       HIPCHK(hipMemcpyAsync(x_out, p->d_xhat.p + sh.xoff, sh.nx * sizeof(float), hipMemcpyDeviceToHost, p->stream));
-    if (y_out) {  // [balance | AC flow rows] then the SOC rows past the link slots
-      const int64_t head = sh.ny_out - (int64_t)p->nets[sh.net].B * sh.T;
+    if (y_out) {  // [balance | AC flow rows] then the SOC and ramp rows past the link slots
+      const int64_t head = sh.ny_out - (int64_t)(p->nets[sh.net].B + p->nets[sh.net].R) * sh.T;
       HIPCHK(hipMemcpyAsync(y_out, p->d_yhat.p + sh.yoff, head * sizeof(double), hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipMemcpyAsync(y_out + head, p->d_yhat.p + sh.yoff + sh.ny - (sh.ny_out - head),
                             (sh.ny_out - head) * sizeof(double), hipMemcpyDeviceToHost, p->stream));
@@ -1513,7 +1546,7 @@ int dispatch_set_start(gp_plan* p, int32_t s, const float* x, const double* y) {
         if (!std::isfinite(y[i])) fail(GP_EINVAL, "y[%lld] is not finite", (long long)i);
     HIPCHK(hipMemcpyAsync(p->d_xhat.p + sh.xoff, x, sh.nx * sizeof(float), hipMemcpyHostToDevice, p->stream));
     if (y) {  // the HVDC link slots between the AC flow rows and the SOC rows stay zero
-      const int64_t head = sh.ny_out - (int64_t)p->nets[sh.net].B * sh.T;
+      const int64_t head = sh.ny_out - (int64_t)(p->nets[sh.net].B + p->nets[sh.net].R) * sh.T;
       HIPCHK(hipMemcpyAsync(p->d_yhat.p + sh.yoff, y, head * sizeof(double), hipMemcpyHostToDevice, p->stream));
       HIPCHK(hipMemcpyAsync(p->d_yhat.p + sh.yoff + sh.ny - (sh.ny_out - head), y + head,
                             (sh.ny_out - head) * sizeof(double), hipMemcpyHostToDevice, p->stream));

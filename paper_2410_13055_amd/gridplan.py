@@ -45,7 +45,8 @@ class gp_network(C.Structure):
                 ("line_beta", C.POINTER(C.c_double)), ("gen_node", C.POINTER(C.c_int32)),
                 ("gen_cost", C.POINTER(C.c_double)), ("gen_emis", C.POINTER(C.c_double)),
                 ("batt_node", C.POINTER(C.c_int32)), ("eta_min", C.POINTER(C.c_double)),
-                ("eta_max", C.POINTER(C.c_double)), ("n_hvdc", C.c_int32), ("beta_scales", C.c_int32)]
+                ("eta_max", C.POINTER(C.c_double)), ("n_hvdc", C.c_int32), ("beta_scales", C.c_int32),
+                ("gen_ramp", C.POINTER(C.c_double))]
 
 
 class gp_scenario(C.Structure):
@@ -180,7 +181,9 @@ class _Descriptor:
                 gen_emis=np.ascontiguousarray(n.gen_emis, np.float64),
                 batt_node=np.ascontiguousarray(n.batt_node, np.int32),
                 eta_min=np.ascontiguousarray(n.eta_min, np.float64),
-                eta_max=np.ascontiguousarray(n.eta_max, np.float64))
+                eta_max=np.ascontiguousarray(n.eta_max, np.float64),
+                gen_ramp=None if getattr(n, "gen_ramp", None) is None
+                else np.ascontiguousarray(n.gen_ramp, np.float64))
             self.keep.append(arrs)
             nets[i] = gp_network(
                 n.n_nodes, n.n_lines, n.n_gens, n.n_batt,
@@ -189,7 +192,7 @@ class _Descriptor:
                 _ptr(arrs["gen_cost"], C.c_double), _ptr(arrs["gen_emis"], C.c_double),
                 _ptr(arrs["batt_node"], C.c_int32), _ptr(arrs["eta_min"], C.c_double),
                 _ptr(arrs["eta_max"], C.c_double), int(getattr(n, "n_hvdc", 0)),
-                int(getattr(n, "beta_scales", False)))
+                int(getattr(n, "beta_scales", False)), _ptr(arrs["gen_ramp"], C.c_double))
         scs = (gp_scenario * len(case.scenarios))()
         for i, s in enumerate(case.scenarios):
             av = np.ascontiguousarray(s.avail, np.float32)
