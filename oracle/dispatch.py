@@ -587,7 +587,14 @@ def operating_cost(qp: QP, x: np.ndarray) -> float:
     return primal_objective(qp, x)
 
 
-def planner_objective(qp: QP, x: np.ndarray, omega: float) -> float:
-    """h_s(x) = c_s(x) + omega * emissions(x) (emissions-aware planning,
-    Section 2.1)."""
-    return primal_objective(qp, x) + omega * float(np.dot(qp.emis, x))
+def planner_objective(qp: QP, x: np.ndarray, omega: float, y: Optional[np.ndarray] = None,
+                      lmp: float = 0.0) -> float:
+    """h_s = c_s(x) + omega * emissions(x) (emissions-aware planning,
+    Section 2.1) + lmp * sum_{n,t} pi[n,t] D[n,t] (a planner objective built
+    on the locational marginal prices, Section 2.1: what consumers pay at
+    those prices; y the duals, whose balance block is pi)."""
+    h = primal_objective(qp, x) + omega * float(np.dot(qp.emis, x))
+    if lmp:
+        rs = qp.dims["rs"]["bal"]
+        h += lmp * float(np.dot(qp.e[rs], y[rs]))
+    return h

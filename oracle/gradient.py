@@ -21,6 +21,13 @@ For h = c (no emissions weight) the fit is exact with w = y*, so
 dl/dx_A = -z_A and the gradient is the envelope-theorem value
 -sum_i a_i z_i (z the box multipliers); that identity is a pin.
 
+A planner objective on the prices, h = lmp * sum pi D (Section 2.1 allows
+h_s to depend on the LMPs), needs the derivative of the dual solution: on
+the same system dy = -r (E_F E_F')^+ E_A dx_A, so with
+    v = (E_F E_F')^+ g_y,   g_y = lmp * D on the balance rows,
+    dl/dx_A = -r E_A' v,
+chained through the active bounds like the primal part.
+
 When the constraint matrix depends on the capacities (Section 2.1's
 A_s(eta); here a line's susceptance beta_l(eta_l) in its flow rows), the
 perturbed system gains the terms of dE: with G = dE'y,
@@ -119,7 +126,17 @@ def matrix_terms(qp: D.QP, x: np.ndarray, y: np.ndarray, w: np.ndarray, res: np.
     return out
 
 
-def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
+def lmp_dl_dx(qp: D.QP, free: np.ndarray, lmp: float) -> np.ndarray:
+    """-r E' v with (E_F E_F') v = lmp * D (balance rows): the derivative of
+    lmp * pi'D with respect to the held entries (module docstring)."""
+    _, _, msolve, _ = D._free_factor(qp, free)
+    gy = np.zeros(qp.m)
+    rs = qp.dims["rs"]["bal"]
+    gy[rs] = lmp * qp.e[rs]
+    return -qp.r * (qp.E.T @ msolve(gy))
+
+
+def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float, lmp: float = 0.0) -> dict:
     """d h_s(x*(eta)) / d eta for one scenario via the least-squares adjoint.
 
     Returns the gradient, the envelope value (cost part only), the adjoint w
@@ -136,6 +153,10 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
     if qp.line_dbeta is not None:
         grad += matrix_terms(qp, sol.x, sol.y, w, dl_dx)
         env += matrix_terms(qp, sol.x, sol.y, sol.y, np.zeros(qp.n))
+    if lmp:
+        if qp.line_dbeta is not None:
+            raise NotImplementedError("price objectives with a capacity-dependent matrix")
+        grad += eta_from_active(qp, lmp_dl_dx(qp, free, lmp), at_lo, at_hi)
     # weakly active entries whose bound depends on a capacity make the map kinked
     bscale = 1.0 + np.abs(qp.q).max()
     dep_hi, dep_lo = _dependent(qp)
@@ -146,7 +167,7 @@ def scenario_gradient(qp: D.QP, sol: D.Solution, omega: float) -> dict:
 
 
 def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e-3, js=None,
-                          tol_x: float = 1e-9, tol_z: float = 1e-9) -> dict:
+                          tol_x: float = 1e-9, tol_z: float = 1e-9, lmp: float = 0.0) -> dict:
     """Central differences of h_s along each capacity j in ``js`` (default
     all), from re-solves with the solution's active set held fixed.
 
@@ -186,6 +207,7 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
     held_hi = ~free & ~coll & at_hi
     held_lo = ~free & ~coll & at_lo & ~at_hi
     fin_lo, fin_hi = np.isfinite(qp.lo), np.isfinite(qp.hi)
+    rs_bal = qp.dims["rs"]["bal"]
 
     def ratio(num, den):
         """min over den > 0 of num / den (inf when none)."""
@@ -224,7 +246,7 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
         out["dist"][k] = min(dists)
         out["curv"][k] = qp.r * float(dx @ dx)
         # h(x0 + s h dx) - h(x0) = s h g0'dx + (r/2) h^2 ||dx||^2  (exact for the quadratic)
-        lin = float(g0 @ dx)
+        lin = float(g0 @ dx) + (lmp * float(qp.e[rs_bal] @ dy[rs_bal]) if lmp else 0.0)
         quad = 0.5 * qp.r * h * h * float(dx @ dx)
         vp, vm = h * lin + quad, -h * lin + quad
         out["central"][k] = (vp - vm) / (2 * h)
@@ -236,7 +258,7 @@ def fixed_set_differences(qp: D.QP, sol: D.Solution, omega: float, h: float = 1e
     return out
 
 
-def batch_gradient(case, eta: np.ndarray, scen, omega: float, tol: float = 1e-10):
+def batch_gradient(case, eta: np.ndarray, scen, omega: float, tol: float = 1e-10, lmp: float = 0.0):
     """(1/|scen|) sum_s w_s d h_s / d eta over the listed scenarios, on the
     case-wide capacity vector (investment term gamma excluded).  Also returns
     the weighted mean planner objective and per-scenario results."""
@@ -249,20 +271,20 @@ def batch_gradient(case, eta: np.ndarray, scen, omega: float, tol: float = 1e-10
         a, b = off[sc.network], off[sc.network + 1]
         qp = D.assemble(case, s, eta[a:b])
         sol = D.solve(qp, tol=tol)
-        gr = scenario_gradient(qp, sol, omega)
+        gr = scenario_gradient(qp, sol, omega, lmp)
         out[a:b] += sc.weight * gr["grad"]
-        h = D.planner_objective(qp, sol.x, omega)
+        h = D.planner_objective(qp, sol.x, omega, sol.y, lmp)
         hbar += sc.weight * h
         per.append(dict(qp=qp, sol=sol, grad=gr, h=h))
     nb = len(scen)
     return out / nb, hbar / nb, per
 
 
-def value(case, s: int, eta_net: np.ndarray, omega: float, tol: float = 1e-10) -> float:
+def value(case, s: int, eta_net: np.ndarray, omega: float, tol: float = 1e-10, lmp: float = 0.0) -> float:
     """h_s(x*_s(eta)) from a full polished re-solve."""
     qp = D.assemble(case, s, eta_net)
     sol = D.solve(qp, tol=tol)
-    return D.planner_objective(qp, sol.x, omega)
+    return D.planner_objective(qp, sol.x, omega, sol.y, lmp)
 
 
 def central_difference(case, s: int, eta_net: np.ndarray, j: int, omega: float,
