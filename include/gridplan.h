@@ -29,7 +29,8 @@
  *   ramp:    p[g,t] - p[g,t-1] - s[r,t] = 0, cyclic, for the R units with a
  *            ramp limit, s[r,t] in [-rho_g eta_g, rho_g eta_g]  (dual: kappa)
  *   c_s(x) = sum cost_g p + lambda_u sum u + (r/2) ||x||^2
- *   h_s(x) = c_s(x) + omega * sum emis_g p   (emissions-aware planning)
+ *   h_s(x) = c_s(x) + omega * sum emis_g p   (emissions-aware planning),
+ *            + lmp * sum pi D when a price weight is set (plan_set_price_weight)
  *
  * Canonical per-scenario vector orders (used by the accessors):
  *   x = [p (G*T) | f (L*T) | th (N*T) | ch (B*T) | dis (B*T) | soc (B*T) | u (N*T) | s (R*T)]
@@ -226,6 +227,18 @@ int dispatch_objective(gp_plan* p, const double* eta, const int32_t* scen, int32
 int plan_step(gp_plan* p, double alpha, const int32_t* scen, int32_t nb, const double* gamma,
               double omega, int32_t warm_mode, double* eta_inout, double* phi_out,
               double* delta_out);
+
+/* Weight lmp of a planner objective on the prices (Section 2.1 lets h_s
+ * depend on the LMPs): from this call on, dispatch_grad, dispatch_objective
+ * and plan_step use h_s = c_s + omega * emissions + lmp * sum_{n,t}
+ * pi[n,t] load[n,t] (what consumers pay at the LMPs; lmp may be negative).
+ * Its gradient needs the prices' sensitivity: the adjoint solve then
+ * carries lmp * load on its balance rows (the adjoint runs whenever omega >
+ * 0 or lmp != 0).  Prices that the dispatch does not determine (a node all
+ * of whose terminals are held at bounds) leave that adjoint infeasible and
+ * the call reports GP_ENOTCONVERGED.  0 by default.  Errors: GP_EINVAL (not
+ * finite; at dispatch_grad, a network with beta_scales in the batch). */
+int plan_set_price_weight(gp_plan* p, double lmp);
 
 /* Copy scenario s's last solution (canonical orders above) to host buffers:
  * x_out [n_x] FP32 and y_out [n_y] FP64 (either nullable).  n_x and n_y are

@@ -6,7 +6,7 @@
 
 namespace gp {
 
-constexpr int kStats = 14;  // FP64 statistics per tile / per scenario
+constexpr int kStats = 15;  // FP64 statistics per tile / per scenario
 
 // statistic slots (sums unless noted)
 enum Stat {
@@ -25,6 +25,7 @@ enum Stat {
   ST_DUAL2 = 12,    // sum (E'y - q - r x)^2 over free entries
   ST_D0 = 13,       // dual function at y = 0 (its box terms): the objective's
                     // scale when the optimum is near zero (adjoint solves)
+  ST_PD = 14,       // sum load * pi over balance rows (dispatch solve)
 };
 constexpr int kMaxStats = 5;  // slots [0, kMaxStats) are maxima, the rest sums
 
@@ -154,6 +155,8 @@ struct Args {
   // constants
   float r, lambda_u, eff, hours;
   float omega;              // adjoint mode: emission weight
+  float lmp;                // adjoint mode: weight of sum pi D in the planner
+                            // objective (the adjoint's balance rows carry lmp D)
   Weights w;
   // statistics
   double* part_v;           // [nvt][kStats]

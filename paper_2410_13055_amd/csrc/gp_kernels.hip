@@ -173,7 +173,8 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
   if ((tl.cls & 0xff) == RC_BAL) {
     const int n = i / T, t = i - n * T;
     f4 res = ld4(xs + (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i);
-    if (!a.mode) res -= ld4(a.load + sc.doff + i);
+    // the dispatch rows carry the load; the adjoint's carry lmp * load
+    res -= (a.mode ? a.lmp : 1.f) * ld4(a.load + sc.doff + i);
     const int e0 = a.term_ptr[nt.tptr_off + n], e1 = a.term_ptr[nt.tptr_off + n + 1];
     const float* pf = xs + (int64_t)nt.G * TT;
     const float* pch = xs + (int64_t)(nt.G + nt.L + nt.N) * TT;
@@ -372,7 +373,7 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
   const int i = tl.start + li;
   if (tl.cls == RC_BAL) {
     const int n = i / T, t = i - n * T;
-    const float load = a.mode ? 0.f : a.load[sc.doff + i];
+    const float load = (a.mode ? a.lmp : 1.f) * a.load[sc.doff + i];
     const float res = bal_residual(a, nt, xs, T, n, t, load);
     dual_update(a, sc.yoff + i, c * (double)a.sig_bal[nt.node_off + n] * (double)res, lam, check);
   } else if (tl.cls == RC_RAMP) {
@@ -801,11 +802,12 @@ __global__ __launch_bounds__(BS) void k_check_rows(Args a) {
       int slot = ST_RES_MAX;
       if (tl.cls == RC_BAL) {
         const int n = i / T, t = i - n * T;
-        const float load = a.mode ? 0.f : a.load[sc.doff + i];
+        const float load = (a.mode ? a.lmp : 1.f) * a.load[sc.doff + i];
         res = bal_residual(a, nt, xs, T, n, t, load);
         den = 1.0 / a.sig_bal[nt.node_off + n];
         row = sc.yoff + i;
         v[ST_D] += (double)load * (double)a.yhat[row];
+        if (!a.mode) v[ST_PD] = (double)load * (double)a.yhat[row];
       } else if (tl.cls == RC_RAMP) {
         const int rk = i / T, t = i - rk * T;
         res = ramp_residual(a, nt, xs, T, rk, t);

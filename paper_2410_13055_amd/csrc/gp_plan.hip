@@ -230,6 +230,9 @@ struct gp_plan {
   // solution bookkeeping
   std::vector<int> has_solution;
   std::vector<double> last_cost, last_emis;  // c_s and emissions at each scenario's last solution
+  std::vector<double> last_pd;               // sum pi D at each scenario's last solution
+  std::vector<double> it_pd;                 // the same for the batch entries of the running solve
+  double lmp = 0.0;                          // weight of sum pi D in the planner objective
   std::vector<float> last_cw, last_cwf;
   std::vector<int> cold_iters;  // per network: iterations of its last converged cold solve (0 = none yet)
   std::vector<int> solved_batch;
@@ -599,6 +602,7 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   p->has_solution.assign(p->S, 0);
   p->last_cost.assign(p->S, 0.0);
   p->last_emis.assign(p->S, 0.0);
+  p->last_pd.assign(p->S, 0.0);
   p->last_cw.assign(p->S, 0.f);
   p->last_cwf.assign(p->S, 1.f);
   p->cold_iters.assign(p->nets.size(), 0);
@@ -942,11 +946,11 @@ struct Kkt {
 };
 
 // einf < 0 selects the adjoint scaling: the primal residual is measured
-// relative to the largest entry of the iterate (the adjoint system has a
-// zero right-hand side)
+// relative to the largest entry of the iterate or of the right-hand side,
+// -einf - 1 (zero unless a price objective puts lmp * load there)
 Kkt kkt_of(const gp_plan* p, const double* st, double einf, double e2 = 0.0, double q2 = 1.0) {
   Kkt k;
-  const double den = 1.0 + (einf < 0 ? st[ST_XMAX] : einf);
+  const double den = 1.0 + (einf < 0 ? std::max(st[ST_XMAX], -einf - 1.0) : einf);
   k.r_bal = st[ST_RES_MAX] / den;
   k.r_flow = st[ST_RESF_MAX] / den;
   k.r_soc = st[ST_RESS_MAX] / den;
@@ -958,7 +962,7 @@ Kkt kkt_of(const gp_plan* p, const double* st, double einf, double e2 = 0.0, dou
   const double P = st[ST_P], D = st[ST_D], D0 = st[ST_D0];
   k.r_gap = std::fabs(P - D) / (1.0 + std::max(std::max(std::fabs(P), std::fabs(D)), std::fabs(D0)));
   k.kkt = std::max(k.r_pri, std::max(k.r_dual, k.r_gap));
-  const double rp2 = std::sqrt(st[ST_RES2]) / (1.0 + (einf < 0 ? st[ST_XMAX] : e2));
+  const double rp2 = std::sqrt(st[ST_RES2]) / (1.0 + (einf < 0 ? std::max(st[ST_XMAX], -einf - 1.0) : e2));
   const double rd2 = std::sqrt(st[ST_DUAL2]) / (1.0 + q2);
   k.kkt2 = std::max(rp2, std::max(rd2, k.r_gap));
   return k;
@@ -972,6 +976,8 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
   const int nb = (int)batch.size();
   Args a = make_args(p, mode);
   a.omega = (float)omega;
+  a.lmp = mode ? (float)p->lmp : 0.f;
+  p->it_pd.assign(nb, 0.0);
   const int ce = std::max(2, p->opt.check_every > 0 ? p->opt.check_every : p->ce);
   const int max_iter = p->opt.max_iter > 0 ? p->opt.max_iter : 400000;
   const double tol = p->opt.tol > 0 ? p->opt.tol : 1e-4;
@@ -1072,6 +1078,7 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
     out[b].kkt = k.kkt;
     out[b].cost = p->h_stats[(size_t)b * kStats + ST_P];
     out[b].emis = p->h_stats[(size_t)b * kStats + ST_EMIS];
+    p->it_pd[b] = p->h_stats[(size_t)b * kStats + ST_PD];
   }
   int remaining = 0;
   for (int b = 0; b < nb; ++b) remaining += !done[b];
@@ -1096,6 +1103,7 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       out[b].kkt = k.kkt;
       out[b].cost = st[ST_P];
       out[b].emis = st[ST_EMIS];
+      p->it_pd[b] = st[ST_PD];
       out[b].iters = total[b];
       const int pct = p->opt.stall_pct > 0 ? p->opt.stall_pct : 100;
       const int ref = mode == 0 ? (int)std::min<int64_t>((int64_t)p->cold_iters[p->scen[s].net] * pct / 100, INT32_MAX) : 0;
@@ -1288,6 +1296,7 @@ int solve_impl(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, i
     p->has_solution[batch[b]] = 1;
     p->last_cost[batch[b]] = st[b].cost;
     p->last_emis[batch[b]] = st[b].emis;
+    p->last_pd[batch[b]] = p->it_pd[b];
     if (cost_out) cost_out[b] = st[b].cost;
     if (stats_out) stats_out[b] = st[b];
   }
@@ -1313,6 +1322,10 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
   if (!grad_out) fail(GP_EINVAL, "grad_out is NULL");
   if (!std::isfinite(omega) || omega < 0) fail(GP_EINVAL, "omega must be finite and >= 0");
   check_last_solve(p, batch, eta, "dispatch_grad");
+  if (p->lmp != 0.0)
+    for (int s : batch)
+      if (p->nets[p->scen[s].net].scales)
+        fail(GP_EINVAL, "a price objective on a network whose susceptances scale with capacity is not supported");
   build_tiles(p, batch);
   hipStream_t st = p->stream;
   // objective parts of the forward solution
@@ -1321,10 +1334,11 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
   upload_control(p);
   Args a = make_args(p, 0);
   run_check_only(p, a);
-  std::vector<double> cost(nb), emis(nb);
+  std::vector<double> cost(nb), emis(nb), pd(nb);
   for (int b = 0; b < nb; ++b) {
     cost[b] = p->h_stats[(size_t)b * kStats + ST_P];
     emis[b] = p->h_stats[(size_t)b * kStats + ST_EMIS];
+    pd[b] = p->h_stats[(size_t)b * kStats + ST_PD];
   }
   // active-bound mask of the forward solution
   HIPCHK(launch_mask(a, block_size(p), p->d_mask.p, st));
@@ -1348,8 +1362,9 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
   std::vector<double> g(ndev);
   std::copy(p->h_gpart.p, p->h_gpart.p + ndev, g.begin());
   int rc = GP_OK;
-  if (omega > 0) {
-    // emissions part: adjoint QP with the active set held fixed
+  if (omega > 0 || p->lmp != 0.0) {
+    // emissions and price parts: one adjoint QP with the active set held
+    // fixed, emission rates as its costs and lmp * load on its balance rows
     if (!p->a_x.p) {
       p->a_x.alloc(p->nx_tot);
       p->a_x0.alloc(p->nx_tot);
@@ -1364,7 +1379,8 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
       HIPCHK(hipMemsetAsync(p->a_yhat.p, 0, p->ny_tot * sizeof(double), st));
     }
     drop_graph(p);
-    std::vector<double> einf(nb, -1.0);
+    std::vector<double> einf(nb);
+    for (int b = 0; b < nb; ++b) einf[b] = -1.0 - std::fabs(p->lmp) * p->scen[batch[b]].einf;
     std::vector<gp_solve_stats> ast;
     const int rem = iterate(p, 1, einf, 0, ast, omega);
     drop_graph(p);
@@ -1385,7 +1401,7 @@ int grad_impl(gp_plan* p, const int32_t* scen, int32_t nb, const double* eta, do
     const NetHost& n = p->nets[sh.net];
     const int Kn = n.G + n.L + n.B;
     for (int j = 0; j < Kn; ++j) grad_out[n.eta_off + j] += sh.weight * g[goff[b] + j] / nb;
-    h += sh.weight * (cost[b] + omega * emis[b]) / nb;
+    h += sh.weight * (cost[b] + omega * emis[b] + p->lmp * pd[b]) / nb;
   }
   if (h_out) *h_out = h;
   return rc;
@@ -1465,6 +1481,15 @@ int dispatch_grad(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb
   return guarded(p, [&] { return grad_impl(p, scen, nb, eta, omega, grad_out, h_out); });
 }
 
+int plan_set_price_weight(gp_plan* p, double lmp) {
+  if (!p) return GP_EINVAL;
+  return guarded(p, [&] {
+    if (!std::isfinite(lmp)) fail(GP_EINVAL, "the price weight must be finite");
+    p->lmp = lmp;
+    return GP_OK;
+  });
+}
+
 int dispatch_objective(gp_plan* p, const double* eta, const int32_t* scen, int32_t nb, double omega,
                        double* h_out) {
   if (!p) return GP_EINVAL;
@@ -1474,9 +1499,10 @@ int dispatch_objective(gp_plan* p, const double* eta, const int32_t* scen, int32
     if (!h_out) fail(GP_EINVAL, "h_out is NULL");
     if (!std::isfinite(omega) || omega < 0) fail(GP_EINVAL, "omega must be finite and >= 0");
     check_last_solve(p, batch, eta, "dispatch_objective");
-    // (1/nb) sum_s w_s (c_s + omega emis_s), fixed summation order
+    // (1/nb) sum_s w_s (c_s + omega emis_s + lmp pi'D), fixed summation order
     double h = 0.0;
-    for (int s : batch) h += p->scen[s].weight * (p->last_cost[s] + omega * p->last_emis[s]) / nb;
+    for (int s : batch)
+      h += p->scen[s].weight * (p->last_cost[s] + omega * p->last_emis[s] + p->lmp * p->last_pd[s]) / nb;
     *h_out = h;
     return GP_OK;
   });

@@ -20,6 +20,7 @@ GP_OK, GP_ENOTCONVERGED = 0, 1
 GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_ESTATE = -1, -2, -3, -4
 
 EXPORTS = ("plan_init", "dispatch_solve_batch", "dispatch_grad", "dispatch_objective", "plan_step",
+           "plan_set_price_weight",
            "dispatch_get_solution", "dispatch_set_start", "plan_time_sweeps", "plan_tuning",
            "plan_nn_rows", "plan_features", "plan_targets", "plan_start_from_prediction",
            "mlp_init", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward", "mlp_forward_noalloc",
@@ -101,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.dispatch_objective.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int32), C.c_int32, C.c_double,
                                        P(C.c_double)]
     lib.dispatch_objective.restype = C.c_int
+    lib.plan_set_price_weight.argtypes = [C.c_void_p, C.c_double]
+    lib.plan_set_price_weight.restype = C.c_int
     lib.plan_step.argtypes = [C.c_void_p, C.c_double, P(C.c_int32), C.c_int32, P(C.c_double),
                               C.c_double, C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.plan_step.restype = C.c_int
@@ -303,6 +306,10 @@ class Plan:
         self._check(self.lib.dispatch_objective(self.h, _ptr(e, C.c_double), _ptr(idx, C.c_int32),
                                                 idx.shape[0], float(omega), C.byref(h)), allow_nc=False)
         return float(h.value)
+
+    def set_price_weight(self, lmp: float):
+        """plan_set_price_weight: h_s gains lmp * sum pi D."""
+        self._check(self.lib.plan_set_price_weight(self.h, float(lmp)), allow_nc=False)
 
     def step(self, alpha, scen, gamma, eta, omega: float = 0.0, warm: int = 1):
         """plan_step: returns (new eta, phi at the input eta, Delta, rc)."""

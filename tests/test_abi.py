@@ -115,6 +115,7 @@ def test_null_arguments():
     assert lib.dispatch_solve_batch(None, None, None, 0, 0, None, None) == gpb.GP_EINVAL
     assert lib.dispatch_grad(None, None, None, 0, 0.0, None, None) == gpb.GP_EINVAL
     assert lib.dispatch_objective(None, None, None, 0, 0.0, None) == gpb.GP_EINVAL
+    assert lib.plan_set_price_weight(None, 1.0) == gpb.GP_EINVAL
     lib.plan_free(None)
 
 
