@@ -25,6 +25,7 @@ stores, as JSON:
 
     python tests/golden/make_golden.py 1 0 1      # config 1, scenarios 0 and 1
     python tests/golden/make_golden.py 3 1        # config 3, scenario 1 (subset mode)
+    python tests/golden/make_golden.py 3 0 --all  # config 3, differences on every capacity
 
 For the 500-node workload (config 3) a back-solve of the reduced system costs
 seconds, so the differences are taken on 40 stratified candidates only (12
@@ -108,8 +109,10 @@ def subset20(case, grad, ok):
 
 
 def main():
-    cfg = int(sys.argv[1])
-    scen = [int(s) for s in sys.argv[2:]] or [0]
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    every = "--all" in sys.argv   # differences on every capacity even for config 3
+    cfg = int(args[0])
+    scen = [int(s) for s in args[1:]] or [0]
     case = cases.by_id(cfg)
     eta = golden_eta(case)
     off = case.eta_offsets()
@@ -121,7 +124,7 @@ def main():
         t_solve = time.time() - t0
         res = D.kkt_residual(qp, sol.x, sol.y)
         gr = Gm.scenario_gradient(qp, sol, case.omega)
-        subset_mode = cfg == 3
+        subset_mode = cfg == 3 and not every
         js = candidates40(case, gr["grad"]) if subset_mode else None
         fd_s = Gm.fixed_set_differences(qp, sol, case.omega, h=FD_H, js=js)
         wide_s = Gm.fixed_set_differences(qp, sol, case.omega, h=WIDE_H, js=js)
