@@ -206,7 +206,7 @@ def summarize(stats_csv, pmc_runs, workload_id, commands):
         blk = info["block"]
         out += [f"Block {blk}: calibration 1 GiB fill reads WRITE_SIZE = {fill_w / gib:.4f} GiB (write factor "
                 f"{fw:.4f}); 1 GiB sum reads FETCH_SIZE = {sum_r / gib:.4f} GiB (read factor {fr:.4f}).", "",
-                "| kernel | FETCH KiB | WRITE KiB | traffic bytes (scaled) | algorithmic bytes |",
+                "| kernel | FETCH KiB | WRITE KiB | traffic bytes (scaled) | design bytes (this layout) |",
                 "|---|---|---|---|---|"]
         sfx = "_q" if info.get("variant") == 2 else ""
         for kern, alg in (("k_primal" + sfx, info["primal"]), ("k_dual" + sfx, info["dual"])):
