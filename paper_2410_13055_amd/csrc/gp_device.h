@@ -88,9 +88,6 @@ struct Weights {
   float wf;     // flow-row copy weight of the line flow
   float wth;    // flow-row copy weight of an angle, per beta^2
   float ws;     // SOC-chain copy weight
-  float wr;     // ramp-row copy weight of a generator output (two per output)
-  float wsr;    // ramp-row copy weight of a ramp variable
-  float sig_ramp;  // 1 / (2/wr + 1/wsr): the ramp rows' dual step
   float sig_flow;  // 1 / (1/wf + 2/wth)
   float rho_f;  // 2 wb + wf
   float rho_b;  // wb + ws  (ch, dis)
@@ -116,9 +113,6 @@ struct Args {
   const int32_t* line_to;
   const float* line_beta;   // susceptance at the current capacities (0 for HVDC links)
   const float* line_dbeta;  // d beta_l / d eta_l (0 unless the line's susceptance scales)
-  const int32_t* gen_ramp;  // per generator: its ramp index (network-local) or -1
-  const int32_t* ramp_gen;  // per ramp index: the generator (network-local)
-  const float* ramp_rho;    // per ramp index: share of capacity per hour
   const int32_t* batt_node;
   const int32_t* term_ptr;
   const int32_t* term;
@@ -155,8 +149,6 @@ struct Args {
   // constants
   float r, lambda_u, eff, hours;
   float omega;              // adjoint mode: emission weight
-  float lmp;                // adjoint mode: weight of sum pi D in the planner
-                            // objective (the adjoint's balance rows carry lmp D)
   Weights w;
   // statistics
   double* part_v;           // [nvt][kStats]
@@ -164,6 +156,16 @@ struct Args {
   const int32_t* ranges;    // [nb][4]: first/last variable tile, first/last row tile
   const int32_t* bscen;     // [nb] scenario of each batch entry
   double* stats;            // [nb][kStats]
+  // (fields below are used by ramp-limited networks and price objectives
+  // only; they sit last so the sweeps' common fields keep their offsets)
+  const int32_t* gen_ramp;  // per generator: its ramp index (network-local) or -1
+  const int32_t* ramp_gen;  // per ramp index: the generator (network-local)
+  const float* ramp_rho;    // per ramp index: share of capacity per hour
+  float lmp;                // adjoint mode: weight of sum pi D in the planner
+                            // objective (the adjoint's balance rows carry lmp D)
+  float wr;                 // ramp-row copy weight of a generator output (two per output)
+  float wsr;                // ramp-row copy weight of a ramp variable
+  float sig_ramp;           // 1 / (2/wr + 1/wsr): the ramp rows' dual step
 };
 
 }  // namespace gp

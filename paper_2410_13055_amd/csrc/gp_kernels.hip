@@ -174,7 +174,8 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
     const int n = i / T, t = i - n * T;
     f4 res = ld4(xs + (int64_t)(nt.G + nt.L + nt.N + 3 * nt.B) * TT + i);
     // the dispatch rows carry the load; the adjoint's carry lmp * load
-    res -= (a.mode ? a.lmp : 1.f) * ld4(a.load + sc.doff + i);
+    if (!a.mode) res -= ld4(a.load + sc.doff + i);
+    else if (a.lmp != 0.f) res -= a.lmp * ld4(a.load + sc.doff + i);
     const int e0 = a.term_ptr[nt.tptr_off + n], e1 = a.term_ptr[nt.tptr_off + n + 1];
     const float* pf = xs + (int64_t)nt.G * TT;
     const float* pch = xs + (int64_t)(nt.G + nt.L + nt.N) * TT;
@@ -205,18 +206,6 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
 #pragma unroll
     for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
     dual_update4(a, sc.yoff + i, step, lam, check);
-  } else if ((tl.cls & 0xff) == RC_RAMP) {
-    // p[g, t] - p[g, t-1] - s[r, t], cyclic in t
-    const int rk = i / T, t = i - rk * T;
-    const int g = a.ramp_gen[nt.ramp_off + rk];
-    const float* pg = xs + (int64_t)g * TT;
-    const f4 pv = ld4(pg + t);
-    const f4 pp = {pg[t == 0 ? T - 1 : t - 1], pv[0], pv[1], pv[2]};
-    const f4 res = pv - pp - ld4(xs + (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i);
-    const double f = c * (double)a.w.sig_ramp;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
-    dual_update4(a, sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i, step, lam, check);
   } else {  // RC_FLOW
     const int l = i / T, t = i - l * T;
     const int fr = a.line_from[nt.line_off + l], to = a.line_to[nt.line_off + l];
@@ -228,6 +217,28 @@ __device__ __forceinline__ void dual_rows4(const Args& a, const Tile& tl, const 
     for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
     dual_update4(a, sc.yoff + (int64_t)nt.N * TT + i, step, lam, check);
   }
+}
+
+// Ramp rows, four hours per thread: p[g, t] - p[g, t-1] - s[r, t], cyclic in t.
+__device__ __forceinline__ void ramp_rows4(const Args& a, const Tile& tl, const ScenDev& sc, const NetDev& nt,
+                                           double c, double lam, int check) {
+  const int li = 4 * (int)threadIdx.x;
+  if (li >= tl.count) return;
+  const int i = tl.start + li;
+  const int T = sc.T;
+  const int64_t TT = T;
+  const float* xs = a.x + sc.xoff;
+  const int rk = i / T, t = i - rk * T;
+  const int g = a.ramp_gen[nt.ramp_off + rk];
+  const float* pg = xs + (int64_t)g * TT;
+  const f4 pv = ld4(pg + t);
+  const f4 pp = {pg[t == 0 ? T - 1 : t - 1], pv[0], pv[1], pv[2]};
+  const f4 res = pv - pp - ld4(xs + (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i);
+  const double f = c * (double)a.sig_ramp;
+  double step[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) step[q] = f * (double)res[q];
+  dual_update4(a, sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i, step, lam, check);
 }
 
 // Battery chains, four hours per thread: T/4 threads per chain and as many
@@ -332,6 +343,10 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
     soc_chains4(a, tl, sc, nt, c, lam, check, sres);
     return;
   }
+  if (tl.cls == (RC_RAMP | kTileVec4)) {
+    ramp_rows4(a, tl, sc, nt, c, lam, check);
+    return;
+  }
   if (tl.cls & kTileVec4) {
     dual_rows4(a, tl, sc, nt, c, lam, check);
     return;
@@ -373,13 +388,13 @@ __device__ __forceinline__ void dual_tile(const Args& a, int tix, int j, int che
   const int i = tl.start + li;
   if (tl.cls == RC_BAL) {
     const int n = i / T, t = i - n * T;
-    const float load = (a.mode ? a.lmp : 1.f) * a.load[sc.doff + i];
+    const float load = a.mode ? a.lmp * a.load[sc.doff + i] : a.load[sc.doff + i];
     const float res = bal_residual(a, nt, xs, T, n, t, load);
     dual_update(a, sc.yoff + i, c * (double)a.sig_bal[nt.node_off + n] * (double)res, lam, check);
   } else if (tl.cls == RC_RAMP) {
     const int rk = i / T, t = i - rk * T;
     const float res = ramp_residual(a, nt, xs, T, rk, t);
-    dual_update(a, sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i, c * (double)a.w.sig_ramp * (double)res, lam,
+    dual_update(a, sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i, c * (double)a.sig_ramp * (double)res, lam,
                 check);
   } else {  // RC_FLOW
     const int l = i / T, t = i - l * T;
@@ -489,7 +504,7 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
       ldy4(a, yb + (int64_t)n * TT + t, ey);
       float rho = a.w.wb;
-      const int rk = a.gen_ramp[nt.gen_off + g];
+      const int rk = nt.R > 0 ? a.gen_ramp[nt.gen_off + g] : -1;
       if (rk >= 0) {  // copies in ramp rows t (+1) and t + 1 (-1)
         const int64_t yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
         double nu[4];
@@ -497,7 +512,7 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
         const double nu_next = ldy(a, yr + ((t + 4 == T) ? 0 : t + 4));
 #pragma unroll
         for (int k = 0; k < 4; ++k) ey[k] += nu[k] - (k < 3 ? nu[k + 1] : nu_next);
-        rho += 2.f * a.w.wr;
+        rho += 2.f * a.wr;
       }
       upd4(u, i, ey, q, rho, zero, hi);
       break;
@@ -510,7 +525,7 @@ __device__ __forceinline__ void primal_tile4(const Args& a, const Tile& tl, cons
       ldy4(a, yb + (int64_t)(nt.N + nt.L + nt.B) * TT + i, nu);
 #pragma unroll
       for (int k = 0; k < 4; ++k) ey[k] = -nu[k];
-      upd4(u, (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i, ey, 0.f, a.w.wsr, -hi, hi);
+      upd4(u, (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i, ey, 0.f, a.wsr, -hi, hi);
       break;
     }
     case VC_LINE: {
@@ -610,11 +625,11 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
       const float q = a.mode ? a.omega * a.gen_emis[nt.gen_off + g] : a.gen_cost[nt.gen_off + g];
       double ey = ldy(a, yb + (int64_t)n * TT + t);
       float rho = a.w.wb;
-      const int rk = a.gen_ramp[nt.gen_off + g];
+      const int rk = nt.R > 0 ? a.gen_ramp[nt.gen_off + g] : -1;
       if (rk >= 0) {
         const int64_t yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
         ey += ldy(a, yr + t) - ldy(a, yr + ((t + 1 == T) ? 0 : t + 1));
-        rho += 2.f * a.w.wr;
+        rho += 2.f * a.wr;
       }
       u(i, ey, q, rho, 0.f, hi);
       break;
@@ -623,7 +638,7 @@ __device__ __forceinline__ void primal_tile(const Args& a, int tix, int j, int c
       const int rk = i / T;
       const float cap = a.ramp_rho[nt.ramp_off + rk] * a.eta[nt.eta_off + a.ramp_gen[nt.ramp_off + rk]];
       u((int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i, -ldy(a, yb + (int64_t)(nt.N + nt.L + nt.B) * TT + i),
-        0.f, a.w.wsr, -cap, cap);
+        0.f, a.wsr, -cap, cap);
       break;
     }
     case VC_LINE: {
@@ -811,7 +826,7 @@ __global__ __launch_bounds__(BS) void k_check_rows(Args a) {
       } else if (tl.cls == RC_RAMP) {
         const int rk = i / T, t = i - rk * T;
         res = ramp_residual(a, nt, xs, T, rk, t);
-        den = 1.0 / (double)a.w.sig_ramp;
+        den = 1.0 / (double)a.sig_ramp;
         row = sc.yoff + (int64_t)(nt.N + nt.L + nt.B) * TT + i;
         slot = ST_RESS_MAX;
       } else {
@@ -900,7 +915,7 @@ __global__ __launch_bounds__(BS) void k_check_vars(Args a) {
         if (rk >= 0) {
           const double* yr = yb + (int64_t)(nt.N + nt.L + nt.B) * TT + (int64_t)rk * TT;
           ey += yr[t] - yr[(t + 1 == T) ? 0 : t + 1];
-          rho += 2.0 * a.w.wr;
+          rho += 2.0 * a.wr;
         }
         var_stats(v, xv, x0[i], ey, q, r, lo, hi, rho);
         v[ST_EMIS] += em * xv;
@@ -913,7 +928,7 @@ __global__ __launch_bounds__(BS) void k_check_vars(Args a) {
         const int64_t idx = (int64_t)(nt.G + nt.L + 2 * nt.N + 3 * nt.B) * TT + i;
         double lo = -cap, hi = cap;
         bnd(idx, lo, hi);
-        var_stats(v, xh[idx], x0[idx], -yb[(int64_t)(nt.N + nt.L + nt.B) * TT + i], 0.0, r, lo, hi, a.w.wsr);
+        var_stats(v, xh[idx], x0[idx], -yb[(int64_t)(nt.N + nt.L + nt.B) * TT + i], 0.0, r, lo, hi, a.wsr);
         break;
       }
       case VC_LINE: {

@@ -233,6 +233,7 @@ struct gp_plan {
   std::vector<double> last_pd;               // sum pi D at each scenario's last solution
   std::vector<double> it_pd;                 // the same for the batch entries of the running solve
   double lmp = 0.0;                          // weight of sum pi D in the planner objective
+  float wr = 1.f, wsr = 1.f, sig_ramp = 1.f;  // ramp-row copy weights and dual step
   std::vector<float> last_cw, last_cwf;
   std::vector<int> cold_iters;  // per network: iterations of its last converged cold solve (0 = none yet)
   std::vector<int> solved_batch;
@@ -351,9 +352,9 @@ void build(gp_plan* p, const gp_case_desc* cs) {
   w.wf = 1.f;    // flow-row copy of the line flow
   w.wth = 0.1f;  // flow-row copy of an angle, per beta^2
   w.ws = 1.f;    // SOC-chain copies
-  w.wr = 1.f;    // ramp-row copies of a generator output (rows t and t + 1)
-  w.wsr = 1.f;   // ramp-row copy of a ramp variable
-  w.sig_ramp = 1.f / (2.f / w.wr + 1.f / w.wsr);
+  p->wr = 1.f;   // ramp-row copies of a generator output (rows t and t + 1)
+  p->wsr = 1.f;  // ramp-row copy of a ramp variable
+  p->sig_ramp = 1.f / (2.f / p->wr + 1.f / p->wsr);
   w.sig_flow = 1.f / (1.f / w.wf + 2.f / w.wth);
   w.rho_f = 2.f * w.wb + w.wf;
   w.rho_b = w.wb + w.ws;
@@ -673,6 +674,9 @@ Args make_args(gp_plan* p, int adjoint) {
   a.hours = (float)p->hours;
   a.omega = 0.f;
   a.w = p->w;
+  a.wr = p->wr;
+  a.wsr = p->wsr;
+  a.sig_ramp = p->sig_ramp;
   a.part_v = p->d_part_v.p;
   a.part_r = p->d_part_r.p;
   a.ranges = p->d_ranges.p;
