@@ -11,7 +11,9 @@ second over the timed steps (converged scenarios only).  Beside it: s/step
 of the cold, previous-iterate and learned warm-start arms on the same
 held-out planning run (network trained outside the timed region on planning
 runs at other storage costs), the roofline of one ADMM iteration (the two
-sweep kernels) against the HBM peak with the survey's algorithmic bytes, and
+sweep kernels) against the HBM peak in algorithmic bytes (what one iteration
+must move: every FP32 primal and dual read and written once, every
+time-varying parameter read once), and
 the FP64 CPU oracle timed on the host cores.
 """
 import argparse
@@ -56,7 +58,7 @@ def algorithmic_bytes(case, scen):
     return dict(primal=12 * nx + 12 * ny + 4 * gt, dual=4 * nx + 8 * ny + 4 * nt, n_x=nx, n_y=ny)
 
 
-def sec8d_bytes(case, scen):
+def method_bytes(case, scen):
     """Algorithmic bytes of one ADMM iteration (what the method must move,
     not this design's layout): read and write every FP32 primal (8 n_x),
     every FP32 dual (8 n_eq), and read every time-varying FP32 parameter
@@ -216,9 +218,13 @@ def summarize(stats_csv, pmc_runs, workload_id, commands):
             out.append(f"| `{pre[len('void gp::'):]}` | {f_:.0f} | {w_:.0f} | {traffic:.0f} | {alg} |")
             rows.append((f"{kern}<{blk}>", traffic))
         out.append("")
-    h = kernel_source_hash()
+    # the hash of the kernel sources the counter runs executed (recorded by
+    # the runs themselves), so a summary written later cannot vouch for
+    # kernels changed since
+    hashes = {json.loads(line).get("source_hash", "unrecorded") for _, _, line in runs}
+    h = hashes.pop() if len(hashes) == 1 else "mixed"
     table = ["# HBM traffic per launch of the sweep kernels", "",
-             f"From the counter runs summarised in `profiles/sweeps_geo240.md`; kernel source hash {h}.",
+             f"From the counter runs summarised in `profiles/sweeps_geo1000.md`; kernel source hash {h}.",
              "", "Table read by bench.py (valid while the kernel source hash matches):", "",
              "| key | bytes_per_launch | source_hash |", "|---|---|---|"]
     table += [f"| {k}@config{workload_id} | {t:.0f} | {h} |" for k, t in rows]
@@ -851,7 +857,7 @@ def headline_leg(args):
         g, _, rc2 = p.grad(scen, eta=eta)
         if collect is not None:
             collect.collect(eta, scen)
-        if state["alpha"] is None:  # step size of the survey's reading, from the first gradient
+        if state["alpha"] is None:  # step size from the first gradient (a share of the smallest box)
             state["alpha"] = 0.05 * float((hi - lo).min()) / float(np.abs(gam + g).max())
         return np.clip(eta - state["alpha"] * (gam + g), lo, hi), st, rc, rc2
 
@@ -934,9 +940,9 @@ def headline_leg(args):
     tb16, tv16, _, _ = p16.tuning()
     p16.close()
     ab = algorithmic_bytes(case, scen16)
-    b8d = sec8d_bytes(case, scen16)
+    bm = method_bytes(case, scen16)
     it_ms = md + mp_
-    achieved = b8d / (it_ms * 1e-3) / 1e9
+    achieved = bm / (it_ms * 1e-3) / 1e9
     sfx = "_q" if tv16 == 2 else ""
     tp = measured_traffic("k_primal" + sfx, tb16, 4)
     td = measured_traffic("k_dual" + sfx, tb16, 4)
@@ -944,7 +950,7 @@ def headline_leg(args):
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (tp + td) if (tp is not None and td is not None) else None,
-            "bytes_per_iteration": b8d, "design_bytes_per_iteration": ab["primal"] + ab["dual"],
+            "bytes_per_iteration": bm, "design_bytes_per_iteration": ab["primal"] + ab["dual"],
             "ms_per_iteration": round(it_ms, 5), "ms_dual": round(md, 5), "ms_primal": round(mp_, 5),
             "launch": {"scenarios": 16, "block": tb16, "form": "work queue" if tv16 == 2 else "tile grid"}}
 
@@ -1110,7 +1116,8 @@ def main():
         ab = algorithmic_bytes(case, scen)
         print(json.dumps({"pmc_run": WORKLOADS[args.config] + f" (sweeps over {len(scen)} scenarios)",
                           "ms_dual": md, "ms_primal": mp, "block": tb, "variant": tv, "copy_bytes": 1 << 30,
-                          "sec8d_bytes_per_iteration": sec8d_bytes(case, scen), **ab}), flush=True)
+                          "method_bytes_per_iteration": method_bytes(case, scen),
+                          "source_hash": kernel_source_hash(), **ab}), flush=True)
         plan.close()
         return
     plan = gridplan.Plan(case, gridplan.options(), stream=gridplan.current_stream())
@@ -1141,18 +1148,18 @@ def main():
     md, mp = plan.time_sweeps(scen, args.sweep_iters)
     tb, tv, tce, _ = plan.tuning()
     sfx = "_q" if tv == 2 else ""
-    # one ADMM iteration (row sweep + variable sweep) in the survey's
-    # algorithmic bytes; a working set that fits the 256 MB Infinity Cache
+    # one ADMM iteration (row sweep + variable sweep) in algorithmic bytes
+    # (method_bytes); a working set that fits the 256 MB Infinity Cache
     # makes the rate an effective one, not an HBM one
     ab = algorithmic_bytes(case, scen)
-    b8d = sec8d_bytes(case, scen)
+    bm = method_bytes(case, scen)
     ms = md + mp
-    achieved = b8d / (ms * 1e-3) / 1e9
+    achieved = bm / (ms * 1e-3) / 1e9
     resident = ab["primal"] + ab["dual"]
     roof = {"bound": "hbm" if resident > 256e6 else "effective", "kernel": "k_dual + k_primal (one ADMM iteration)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_iteration": b8d, "design_bytes_per_iteration": resident,
+            "traffic": None, "bytes_per_iteration": bm, "design_bytes_per_iteration": resident,
             "ms_per_iteration": round(ms, 5), "ms_dual": round(md, 5), "ms_primal": round(mp, 5),
             "launch": {"block": tb, "form": "work queue" if tv == 2 else "tile grid",
                        "iterations_per_replay": tce}}

@@ -50,8 +50,8 @@ its exact derivative.  ``fixed_set_differences`` evaluates that difference
 by re-solving the equality system of the active set at eta_j +- h (one
 factorisation, two back-solves per capacity) and verifying the optimality
 signs at both ends; a coordinate whose verification fails on either side
-has a kink within h of eta (the survey of the paper's method calls such
-points non-differentiable; Section 2.2 assumes differentiability).
+has a kink within h of eta: the map is not differentiable there (Section
+2.2 assumes differentiability).
 """
 from __future__ import annotations
 

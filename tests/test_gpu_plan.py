@@ -164,7 +164,7 @@ def test_ten_gradient_steps_track_the_oracle():
     eta = cs.eta_min().copy()
     gamma = cs.gamma()
     with _plan(cs) as p:
-        # step size of the survey's reading: 0.1 * min box width / |Delta0|_inf
+        # step size: 0.1 * min box width / |Delta0|_inf
         p.solve(eta, [0])
         g0, _, _ = p.grad([0])
         alpha = 0.1 * (cs.eta_max() - cs.eta_min()).min() / np.abs(gamma + g0).max()
