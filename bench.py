@@ -221,7 +221,7 @@ def summarize(stats_csv, pmc_runs, workload_id, commands):
     # the hash of the kernel sources the counter runs executed (recorded by
     # the runs themselves), so a summary written later cannot vouch for
     # kernels changed since
-    hashes = {json.loads(line).get("source_hash", "unrecorded") for _, _, line in runs}
+    hashes = {json.loads(line).get("source_hash", "unrecorded") for _, _, line in pmc_runs}
     h = hashes.pop() if len(hashes) == 1 else "mixed"
     table = ["# HBM traffic per launch of the sweep kernels", "",
              f"From the counter runs summarised in `profiles/sweeps_geo1000.md`; kernel source hash {h}.",
