@@ -55,6 +55,8 @@ def test_hvdc_two_node_closed_form():
 def test_mixed_network_against_oracle(T, omega):
     cs = cases.small_geo(n_nodes=12, G=30, B=3, T=T, S=2, seed=7, n_hvdc=2)
     net = cs.networks[0]
+    # links of 5 MW at the lower bound of their box, so they bind
+    net.eta_min[net.n_gens + net.n_ac:net.n_gens + net.n_lines] = 5.0
     eta = cases.jitter(cs.eta_min(), 4, eta_min=cs.eta_min(), eta_max=cs.eta_max())
     with _plan(cs) as p:
         cost, st, rc = p.solve(eta, [0, 1])
@@ -81,6 +83,8 @@ def test_mixed_network_against_oracle(T, omega):
     print(f"[gpu] hvdc T={T} omega={omega}: gradient err {err:.2e}; links gpu {g[links]} oracle {ref[links]}",
           flush=True)
     assert err <= 1e-3
+    assert np.all(ref[links] < 0)
+    assert np.linalg.norm((g - ref)[links]) <= 1e-3 * np.linalg.norm(ref[links])
     assert abs(h - href) <= TOL * abs(href)
 
 

@@ -73,7 +73,11 @@ def test_hvdc_differs_from_the_same_ac_line():
 
 
 def _mixed():
-    return cases.small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, n_hvdc=2)
+    # links of 5 MW at the lower bound of their box, so they bind
+    cs = cases.small_geo(n_nodes=12, G=30, B=3, T=24, S=2, seed=7, n_hvdc=2)
+    net = cs.networks[0]
+    net.eta_min[net.n_gens + net.n_ac:net.n_gens + net.n_lines] = 5.0
+    return cs
 
 
 def test_mixed_network_rows_and_physics():
@@ -101,8 +105,10 @@ def test_mixed_network_rows_and_physics():
     ac = slice(0, net.n_ac)
     np.testing.assert_allclose(f[ac], net.line_beta[ac, None] * (th[net.line_from[ac]] - th[net.line_to[ac]]),
                                atol=1e-7)
-    # the links carry power their endpoints' angles would not explain
+    # the links run at their capacity and carry power their endpoints'
+    # angles would not explain
     dc = slice(net.n_ac, net.n_lines)
+    np.testing.assert_allclose(np.abs(f[dc]).max(axis=1), 5.0, atol=1e-7)
     gap = np.abs(f[dc] - net.line_beta[dc, None] * (th[net.line_from[dc]] - th[net.line_to[dc]]))
     assert gap.max() > 1.0
     res = D.kkt_residual(qp, sol.x, sol.y)
@@ -124,6 +130,7 @@ def test_mixed_network_link_gradient_matches_resolves():
         scale = np.abs(gr).max()
         assert np.abs(fd["central"][ok] - gr[ok]).max() <= 1e-6 * scale
         h = 0.05
+        assert np.all(gr[net.n_gens + net.n_ac:net.n_gens + net.n_lines] < 0)   # the links bind
         for l in range(net.n_ac, net.n_lines):
             j = net.n_gens + l
             vals = []
