@@ -318,7 +318,7 @@ int mlp_forward(gp_mlp* m, const float* X, int64_t rows, int32_t on_device, floa
  * is enqueued on the network's stream and Y_dev is ready when the stream
  * reaches it.  X_dev [rows x n_in] and Y_dev [rows x n_out] are row-major
  * FP32 DEVICE buffers owned by the caller.  rows may not exceed what the
- * array holds for this network (2 * rows * max(n_in rounded up to 8, width)
+ * array holds for this network (2 * rows * max(n_in rounded up to 32, width)
  * BF16 entries): *max_rows (nullable) receives that limit, and larger rows
  * fail with GP_EINVAL (split the call).  Every call on a GPU uses that GPU's
  * one array: calls that overlap on one GPU (several streams, or several
