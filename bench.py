@@ -902,21 +902,22 @@ def headline_leg(args):
     roof_mlp = None
     # training data (previous-iterate planning runs at other storage costs),
     # then the two warm arms; each piece runs only while the budget allows it
-    need_collect = len(args.ws_train_prices) * M * per_step * 1.1
+    Mc = args.collect_steps
+    need_collect = len(args.ws_train_prices) * Mc * per_step * 1.1
     if args.arms and left() > need_collect + 2 * M * per_step + 60:
         ws = LearnedWarmStart(plan, T, seed=0)
         t1 = time.perf_counter()
         for i, price in enumerate(args.ws_train_prices):
             gam_keep = gam
             gam = gamma_for(price)
-            run_arm(plan, "previous", batches(100 + i, M), collect=ws, label=f"collect {price}")
+            run_arm(plan, "previous", batches(100 + i, Mc), collect=ws, label=f"collect {price}")
             gam = gam_keep
         collect_s = time.perf_counter() - t1
         t1 = time.perf_counter()
         losses = ws.train(epochs=args.ws_epochs, batch_rows=4096, lr=1e-3)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t1
-        training = {"storage_costs": args.ws_train_prices, "steps_per_run": M, "batch": B, "rows": ws.rows,
+        training = {"storage_costs": args.ws_train_prices, "steps_per_run": Mc, "batch": B, "rows": ws.rows,
                     "epochs": args.ws_epochs, "loss_first": losses[0], "loss_last": losses[-1],
                     "collect_s": round(collect_s, 1), "train_s": round(train_s, 2),
                     "network": f"{5 * T + 3} -> 512 x3 -> {2 * T}, {ws.net.n_params} parameters"}
@@ -1007,10 +1008,12 @@ def main():
     ap.add_argument("--cpu-hours", type=int, default=8)
     ap.add_argument("--batch", type=int, default=4, help="scenarios per planning step (headline)")
     ap.add_argument("--pool", type=int, default=16, help="scenarios the batches are drawn from (headline)")
-    ap.add_argument("--arm-steps", type=int, default=6, help="steps of the warm-start arms (headline)")
+    ap.add_argument("--arm-steps", type=int, default=10, help="steps of the warm-start arms (headline)")
+    ap.add_argument("--collect-steps", type=int, default=6,
+                    help="steps of each planning run that collects the network's training data (headline)")
     ap.add_argument("--no-arms", dest="arms", action="store_false",
                     help="headline: skip the warm-start arms and their training (profiled runs)")
-    ap.add_argument("--budget", type=float, default=500.0,
+    ap.add_argument("--budget", type=float, default=600.0,
                     help="seconds after which the headline run skips its untimed extras")
     ap.add_argument("--sweep-iters", type=int, default=50)
     ap.add_argument("--pmc-block", type=int, default=256, choices=[128, 256, 512],
