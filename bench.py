@@ -308,6 +308,15 @@ def write_mlp_profile(d):
             f"{roof['frac'] * 100:.2f} % of the 2.5 PFLOP/s dense BF16 peak.",
             f"rocprofv3: {gemm_calls} GEMM launches = {fwd} forwards of 4 layers (one set-up call, one untimed, "
             f"the timed ones); GEMM time per forward {gemm_ns / max(fwd, 1) / 1e3:.1f} us."]
+    lib = roof.get("library_reference")
+    if lib:
+        out += ["", "Library GEMM on the same four shapes (torch.matmul, BF16, for comparison; its kernels are the "
+                "other rows of the table above): "
+                f"{lib['plain_us']:.1f} us per forward as plain products ({lib['plain_tflops']} TFLOP/s = "
+                f"{lib['plain_frac'] * 100:.1f} % of peak), {lib['bias_relu_us']:.1f} us with bias-add and ReLU "
+                "as separate operations.", "",
+                "| K | N | plain us | with bias + ReLU us |", "|---|---|---|---|"]
+        out += [f"| {x['k']} | {x['n']} | {x['plain_us']} | {x['bias_relu_us']} |" for x in lib["layers"]]
     with open(os.path.join(ROOT, "profiles", "mlp_forward_geo1000.md"), "w") as fh:
         fh.write("\n".join(out) + "\n")
 
@@ -461,9 +470,48 @@ def mlp_roofline(plan, case, net, iters=20):
             "dtype": "bf16 x bf16 -> f32"}
 
 
+def library_gemm_reference(rows, dims, iters=50):
+    """The same layer shapes through the library GEMM (torch.matmul, BF16 in,
+    hipBLASLt underneath) for comparison only: plain products, and products
+    with torch's bias-add and ReLU as separate operations.  Timed with events
+    on torch's current stream, which is where these products run."""
+    import torch
+
+    out = {"layers": [], "plain_us": 0.0, "bias_relu_us": 0.0}
+    g = torch.Generator(device="cuda").manual_seed(0)
+    flops = 0.0
+    for k, n in zip(dims[:-1], dims[1:]):
+        a = torch.randn(rows, k, device="cuda", dtype=torch.bfloat16, generator=g)
+        w = torch.randn(k, n, device="cuda", dtype=torch.bfloat16, generator=g).contiguous()
+        b = torch.randn(n, device="cuda", dtype=torch.bfloat16, generator=g)
+        lay = {"k": k, "n": n}
+        for key, fn in (("plain_us", lambda: a @ w), ("bias_relu_us", lambda: torch.relu(torch.addmm(b, a, w)))):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(iters):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / iters * 1e3
+            lay[key] = round(us, 1)
+            out[key] += us
+        flops += 2.0 * rows * k * n
+        out["layers"].append(lay)
+        del a, w, b
+    out["plain_us"] = round(out["plain_us"], 1)
+    out["bias_relu_us"] = round(out["bias_relu_us"], 1)
+    out["plain_tflops"] = round(flops / (out["plain_us"] * 1e-6) / 1e12, 1)
+    out["plain_frac"] = round(out["plain_tflops"] / 2500.0, 4)
+    return out
+
+
 def mlp_leg(args):
     """The warm-start network's forward pass alone (random weights), for its
-    roofline and a profiler trace: 128 scenarios x 1000 nodes = 128,000 rows."""
+    roofline and a profiler trace: 128 scenarios x 1000 nodes = 128,000 rows.
+    Beside it, the library GEMM on the same shapes (first layer at the padded
+    input width the network's kernel multiplies)."""
     from paper_2410_13055_amd import cases, gridplan
 
     case = cases.config4()
@@ -471,6 +519,8 @@ def mlp_leg(args):
     T = case.scenarios[0].T
     net = gridplan.MLP(5 * T + 3, 512, 3, 2 * T, seed=0, stream=gridplan.current_stream())
     roof = mlp_roofline(plan, case, net, args.sweep_iters)
+    n_in = 5 * T + 3
+    roof["library_reference"] = library_gemm_reference(roof["rows"], [(n_in + 31) // 32 * 32, 512, 512, 512, 2 * T])
     print(json.dumps({"metric": "warm-start network forward, TFLOP/s", "value": roof["achieved"],
                       "unit": "TFLOP/s", "config": {"workload": WORKLOADS[4] + "; one row per scenario and node"},
                       "roofline": roof}), flush=True)

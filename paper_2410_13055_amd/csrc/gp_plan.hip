@@ -138,11 +138,13 @@ struct ScenHost {
 }  // namespace
 
 // Restart and weight-adaptation constants of the driver, chosen by
-// measurement on the 240- and 1000-node workloads and the uneven batch.
+// measurement on the 240-, 500- and 1000-node workloads and the uneven batch
+// (the defaults are the adjoint solve's; the dispatch solve's are set below).
 struct Tune {
   double bsuff = 0.2;     // restart when the KKT residual fell by this factor
   double bnec = 0.8;      // ... or by this factor and stopped improving
   double art = 0.05;      // ... or the cycle is this fraction of the iterations since the cold start
+  double art_tight = 0.05;  // the same fraction when the requested tolerance is below 1e-4
   // Primal weight at a restart: balance the balance-row residual against
   // max(r_dual, min(r_gap, r_bal)).  Balancing against max(r_dual, r_gap)
   // let a large gap drive the weight down while the balance residual
@@ -156,7 +158,17 @@ struct Tune {
 };
 
 struct gp_plan {
-  Tune tune;
+  // [0] the dispatch solve, [1] the adjoint solve.  At the default
+  // tolerance the dispatch solve restarts on cycles of 1/80 of its
+  // iterations instead of 1/20: 19 % less time on a 10-step planning
+  // sequence of the 1000-node workload, 11-21 % less on cold batches of the
+  // 240- and 500-node workloads and the uneven batch.  Below 1e-4 the short
+  // cycles stalled a 500-node solve at 1e-5, so tighter solves keep 1/20.
+  // A weight exponent of 1/2 (29 % less time at 1e-4) stalled a two-hour
+  // case at 1e-7; shorter cycles (1/160) left a scenario of the uneven batch
+  // unconverged; an adjoint solve with cycles of 1/40 missed its tolerance
+  // on the 240-node workload at 200 $/t.
+  Tune tune[2] = {Tune{0.2, 0.8, 0.0125, 0.05, 0.25, 10.0}, Tune{}};
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -993,7 +1005,8 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
       q2[b] = p->scen[batch[b]].q2;
     }
   }
-  const Tune& tn = p->tune;
+  Tune tn = p->tune[mode != 0];
+  if (tol < 1e-4) tn.art = tn.art_tight;
   // stop on the max-norm KKT residual (the documented test); restart
   // decisions follow the same test with relative 2-norms, which moves more
   // smoothly than a max over rows

@@ -74,22 +74,27 @@ def envelope_on_point(qp, eta_net, x, y):
     return out
 
 
-@pytest.mark.parametrize("cfg,s,bar", [(1, 0, 1e-3), (1, 1, 1e-2), (3, 0, 1e-3), (3, 1, 1e-3)])
-def test_full_size_against_stored_oracle(cfg, s, bar):
-    """Cost gap <= 1e-4 at the 1e-4 KKT tolerance; the gradient pass equal
-    to the oracle's envelope on the GPU's point (h = c); the gradient against
+@pytest.mark.parametrize("cfg,s,tol,bar", [(1, 0, 1e-4, 1e-3), (1, 1, 1e-4, 1e-2), (3, 0, 1e-4, 1e-3),
+                                            (3, 1, 5e-5, 1e-3)])
+def test_full_size_against_stored_oracle(cfg, s, tol, bar):
+    """Cost gap <= 1e-4 at KKT tolerance `tol`; the gradient pass equal to
+    the oracle's envelope on the GPU's point (h = c); the gradient against
     the exact oracle gradient over the differentiable coordinates within
     `bar` (norm-wise), and every coordinate within the bound its duality gap
-    certifies.  Config 1 scenario 1 gets 1e-2: its prices in one pocket
-    (two nodes, hours 3-10, tied to two battery chains) sit in a direction
-    along which the dual function is nearly flat; a 1e-5 solve leaves them
-    off as far as a 1e-4 one, and the resulting gradient error (7.3e-3) does
-    not shrink with the tolerance."""
+    certifies.  The gradient is exact on the point the solve returns, so its
+    error is the point's: config 3 scenario 1 (carbon-priced, adjoint
+    included) measured 8.7e-4 and 1.03e-3 after 1e-4 solves under two
+    restart schedules, so its 1e-3 check is made on a 5e-5 solve.
+    Config 1 scenario 1 gets 1e-2: its prices in one pocket (two nodes,
+    hours 3-10, tied to two battery chains) sit in a direction along which
+    the dual function is nearly flat; a 1e-5 solve leaves them off as far as
+    a 1e-4 one, and the resulting gradient error (7.3e-3) does not shrink
+    with the tolerance."""
     gd = _golden(cfg, s)
     case = cases.by_id(cfg)
     eta = _golden_eta(case)
     omega = case.omega
-    with _plan(case) as p:
+    with _plan(case, tol=tol) as p:
         cost, st, rc = p.solve(eta, [s])
         assert rc == 0, st
         g, h, rc2 = p.grad([s], omega, eta=eta)
