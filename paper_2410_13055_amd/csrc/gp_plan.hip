@@ -154,21 +154,23 @@ struct Tune {
   // rule balancing the weighted primal and dual movement let adjoint solves
   // on the 100-node case diverge).
   double gain = 0.25;     // exponent of the residual-balancing update
+  double gain_tight = 0.25;  // the same exponent when the requested tolerance is below 1e-4
   double clamp = 10.0;    // largest factor of one weight update
 };
 
 struct gp_plan {
   // [0] the dispatch solve, [1] the adjoint solve.  At the default
   // tolerance the dispatch solve restarts on cycles of 1/80 of its
-  // iterations instead of 1/20: 19 % less time on a 10-step planning
-  // sequence of the 1000-node workload, 11-21 % less on cold batches of the
-  // 240- and 500-node workloads and the uneven batch.  Below 1e-4 the short
-  // cycles stalled a 500-node solve at 1e-5, so tighter solves keep 1/20.
-  // A weight exponent of 1/2 (29 % less time at 1e-4) stalled a two-hour
-  // case at 1e-7; shorter cycles (1/160) left a scenario of the uneven batch
+  // iterations instead of 1/20 and moves its weights with exponent 1/2
+  // instead of 1/4: 29 % less time on a 10-step planning sequence of the
+  // 1000-node workload, 11-24 % less on cold batches of the 240- and
+  // 500-node workloads and the uneven batch.  Below 1e-4 they stalled solves
+  // (a 500-node one at 1e-5 with the short cycles, a two-hour case at 1e-7
+  // with both), so tighter solves keep 1/20 and 1/4.  Shorter cycles (1/160)
+  // or cycles of 1/40 with exponent 1/2 left a scenario of the uneven batch
   // unconverged; an adjoint solve with cycles of 1/40 missed its tolerance
   // on the 240-node workload at 200 $/t.
-  Tune tune[2] = {Tune{0.2, 0.8, 0.0125, 0.05, 0.25, 10.0}, Tune{}};
+  Tune tune[2] = {Tune{0.2, 0.8, 0.0125, 0.05, 0.5, 0.25, 10.0}, Tune{}};
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -1006,7 +1008,10 @@ int iterate(gp_plan* p, int mode, const std::vector<double>& einf, int warm,
     }
   }
   Tune tn = p->tune[mode != 0];
-  if (tol < 1e-4) tn.art = tn.art_tight;
+  if (tol < 1e-4) {
+    tn.art = tn.art_tight;
+    tn.gain = tn.gain_tight;
+  }
   // stop on the max-norm KKT residual (the documented test); restart
   // decisions follow the same test with relative 2-norms, which moves more
   // smoothly than a max over rows
