@@ -348,7 +348,7 @@ def write_timeline_profile(d):
            "autotuning included)", "",
            "Command (from /tmp, TMPDIR=/tmp):", "",
            "    rocprofv3 --kernel-trace --output-format csv -d <out>/trace_gap -o run -- "
-           "python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu --no-hbm-case",
+           "python3 <repo>/bench.py --config 1 --steps 1 --warmup 0 --no-cpu --no-hbm-case",
            "    python bench.py --summarize <out>", "",
            f"From the first to the last sweep launch: {span / 1e6:.1f} ms, {len(inside)} kernels, GPU busy "
            f"{busy / 1e6:.1f} ms ({100.0 * busy / span:.1f} %).  Gaps above 20 us between kernels: {len(big)}, "
