@@ -1093,7 +1093,7 @@ def main():
                     help="s/gradient step on the 1000-node workload: cold vs learned warm vs previous-iterate")
     ap.add_argument("--ws-pool", type=int, default=16)
     ap.add_argument("--ws-batch", type=int, default=4)
-    ap.add_argument("--ws-steps", type=int, default=6)
+    ap.add_argument("--ws-steps", type=int, default=10)
     ap.add_argument("--ws-epochs", type=int, default=150)
     ap.add_argument("--ws-train-prices", type=float, nargs="+", default=[100.0, 400.0])
     ap.add_argument("--ws-held-price", type=float, default=250.0)
