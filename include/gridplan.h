@@ -122,7 +122,10 @@ typedef struct {
 /* Solver options.  Zero-initialise and set what you need; zero fields take
  * the defaults given in brackets. */
 typedef struct {
-  double tol;            /* relative KKT residual target [1e-4] */
+  double tol;            /* relative KKT residual target [1e-4]; at 1e-4
+                            and above the dispatch solve restarts and
+                            re-weights more often than below it, where the
+                            frequent schedule stalled tight solves */
   int32_t max_iter;      /* per solve [400000] */
   int32_t check_every;   /* iterations per graph replay and convergence
                             check; 0 = chosen by the autotuner from
