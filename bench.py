@@ -51,11 +51,27 @@ def algorithmic_bytes(case, scen):
         sc = case.scenarios[s]
         n = case.networks[sc.network]
         T = sc.T
-        nx += (n.n_gens + n.n_lines + 2 * n.n_nodes + 3 * n.n_batt) * T
-        ny += (n.n_nodes + n.n_ac + n.n_batt) * T
+        nx += _n_vars(n) * T
+        ny += _n_rows(n) * T
         gt += n.n_gens * T
         nt += n.n_nodes * T
     return dict(primal=12 * nx + 12 * ny + 4 * gt, dual=4 * nx + 8 * ny + 4 * nt, n_x=nx, n_y=ny)
+
+
+def _n_ramped(n):
+    gr = getattr(n, "gen_ramp", None)
+    return 0 if gr is None else int((gr > 0).sum())
+
+
+def _n_vars(n):
+    """Variables per hour: outputs, flows, angles, unserved load, battery
+    charge/discharge/state, ramps of ramp-limited units."""
+    return n.n_gens + n.n_lines + 2 * n.n_nodes + 3 * n.n_batt + _n_ramped(n)
+
+
+def _n_rows(n):
+    """Equality rows per hour: balance, AC flow, SOC chain, ramp."""
+    return n.n_nodes + n.n_ac + n.n_batt + _n_ramped(n)
 
 
 def method_bytes(case, scen):
@@ -68,8 +84,8 @@ def method_bytes(case, scen):
         sc = case.scenarios[s]
         n = case.networks[sc.network]
         T = sc.T
-        nx = (n.n_gens + n.n_lines + 2 * n.n_nodes + 3 * n.n_batt) * T
-        ny = (n.n_nodes + n.n_ac + n.n_batt) * T
+        nx = _n_vars(n) * T
+        ny = _n_rows(n) * T
         tot += 8 * nx + 8 * ny + 4 * (n.n_gens + n.n_nodes) * T
     return tot
 
