@@ -35,7 +35,7 @@ class CapacityCost(torch.autograd.Function):
     def backward(ctx, gout: torch.Tensor):
         plan = ctx.plan
         try:
-            g, _, _ = plan.grad(ctx.scen, ctx.omega, eta=ctx.eta)
+            g, _, rc = plan.grad(ctx.scen, ctx.omega, eta=ctx.eta)
         except gridplan.GridplanError as e:
             if e.code != gridplan.GP_ESTATE:
                 raise
@@ -43,7 +43,10 @@ class CapacityCost(torch.autograd.Function):
             # forward: re-solve this one from its stored solutions, then
             # differentiate
             plan.solve(ctx.eta, ctx.scen, 1)
-            g, _, _ = plan.grad(ctx.scen, ctx.omega, eta=ctx.eta)
+            g, _, rc = plan.grad(ctx.scen, ctx.omega, eta=ctx.eta)
+        if rc != gridplan.GP_OK:
+            warnings.warn("the adjoint solve of the emissions gradient missed the tolerance; the gradient is "
+                          "that of the unconverged adjoint point", RuntimeWarning, stacklevel=2)
         gt = torch.from_numpy(np.ascontiguousarray(g)).to(gout.device, gout.dtype)
         return gout * gt, None, None, None, None
 
